@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Throughput of the direct-summation force evaluation on one MI355X.
+
+Workload: Plummer sphere N = 2^20 with Salpeter masses (0.1-100, slope
+-2.35, total mass 1), eps = 1e-4, neighbour radius 0.01; all j-particles last
+corrected at t = 0 and predicted to t = 2^-10; the active block is all 2^20
+particles (override with --log2ni).  One step is one pass of the whole force
+path on data already resident in GPU memory: j-prediction, the pair
+interaction with nearest neighbour and neighbour lists, and the reduction.
+
+Prints one JSON line: pair interactions/s (value) and Gflop/s at 60 flop per
+interaction (the paper's convention, Sec. 3.1), the interaction kernel's
+fraction of the vector-ALU roofline measured with HIP events on the launch
+stream, the float64 variant's throughput, error statistics of a sample
+against the CPU oracle, and the oracle's own rate on the host cores.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FLOP_PER_PAIR = 60          # Sec. 3.1 convention, used for every variant
+PEAK_FP32_TFLOPS = 157.3    # MI355X vector FP32 (dense)
+PEAK_FP64_TFLOPS = 78.6     # MI355X vector FP64
+METRIC = "pair interactions/s & Gflop/s (60 flop/pair) at N=2^20, DS vs FP64 at stated err"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--log2n", type=int, default=20)
+    ap.add_argument("--log2ni", type=int, default=None, help="active block 2^k (default: all N)")
+    ap.add_argument("--variant", default="ds", choices=["ds", "fp32", "fp64"])
+    ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-neighbour-lists", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target oracle time of the CPU baseline")
+    ap.add_argument("--shape", default=None, help="i_per_group,j_splits override")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the force path is not sharded "
+              "across GPUs", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_0902_4463_amd as g6
+    import workloads
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    n = 2 ** args.log2n
+    log(f"[bench] generating Plummer/Salpeter N={n}")
+    jm = workloads.config_c3(n=n)
+    eps2, h2, ti = jm.meta["eps2"], jm.meta["h2"], jm.meta["ti"]
+    ni = n if args.log2ni is None else 2 ** args.log2ni
+    slots = np.arange(n, dtype=np.int32) if ni == n else workloads.active_set(n, ni, seed=3)
+
+    hid = 0
+    g6.check(hid, g6.g6_open(hid))
+    info = g6.g6mi_device_info(hid)
+    t = {k: torch.tensor(getattr(jm, k), device=dev) for k in ("t", "m", "index", "x", "v", "a2", "j6")}
+    g6.check(hid, g6.g6mi_set_j_particles_device(hid, n, t["t"], t["m"], t["index"], t["x"], t["v"], t["a2"],
+                                                t["j6"]))
+    g6.g6_set_ti(hid, ti)
+    g6.check(hid, g6.g6mi_set_neighbour_lists(hid, not args.no_neighbour_lists))
+    if args.shape:
+        a, b = (int(q) for q in args.shape.split(","))
+        g6.check(hid, g6.g6mi_set_shape(hid, a, b))
+    islot = torch.tensor(slots, device=dev)
+    xi = t["x"][islot.long()].contiguous()
+    vi = t["v"][islot.long()].contiguous()
+    th2 = torch.full((ni,), h2, dtype=torch.float64, device=dev)
+    out = dict(acc=torch.empty((ni, 3), dtype=torch.float64, device=dev),
+               jerk=torch.empty((ni, 3), dtype=torch.float64, device=dev),
+               pot=torch.empty(ni, dtype=torch.float64, device=dev),
+               nnb=torch.empty(ni, dtype=torch.int32, device=dev),
+               r2nn=torch.empty(ni, dtype=torch.float64, device=dev))
+    stream = torch.cuda.current_stream()
+
+    def step():
+        g6.check(hid, g6.g6mi_calc_device(hid, n, ni, islot, xi, vi, eps2, th2, out["acc"], out["jerk"],
+                                          out["pot"], out["nnb"], out["r2nn"], stream=stream))
+
+    def run(variant, steps, warmup):
+        g6.check(hid, g6.g6mi_set_precision(hid, variant))
+        for w in range(warmup):
+            step()
+            torch.cuda.synchronize()
+            log(f"[bench] {variant} warmup {w + 1}/{warmup} done")
+        g6.check(hid, g6.g6mi_enable_timing(hid, 1))
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        w0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        ms = e0.elapsed_time(e1)
+        tot = g6.g6mi_timing_totals(hid)
+        g6.check(hid, g6.g6mi_enable_timing(hid, 0))
+        shape = g6.g6mi_get_shape(hid)
+        res = {k: v.cpu().numpy().copy() for k, v in out.items()}
+        log(f"[bench] {variant}: {steps} steps in {ms:.1f} ms (wall {wall * 1e3:.1f} ms), "
+            f"force kernel {tot['force_ms'] / max(1, tot['count']):.3f} ms avg, shape {shape}")
+        return dict(ms_per_step=ms / steps, force_ms=tot["force_ms"] / max(1, tot["count"]),
+                    predict_ms=tot["predict_ms"] / max(1, tot["count"]),
+                    reduce_ms=tot["reduce_ms"] / max(1, tot["count"]), shape=shape, res=res,
+                    wall_s=wall)
+
+    pairs = float(ni) * float(n)
+    main_run = run(args.variant, args.steps, args.warmup)
+    value = pairs / (main_run["ms_per_step"] * 1e-3)
+    force_tflops = FLOP_PER_PAIR * pairs / (main_run["force_ms"] * 1e-3) / 1e12
+    peak = PEAK_FP64_TFLOPS if args.variant == "fp64" else PEAK_FP32_TFLOPS
+    roofline = dict(bound="alu", achieved=round(force_tflops, 3), peak=peak, unit="TFLOP/s",
+                    frac=round(force_tflops / peak, 4), traffic=None,
+                    kernel=f"force_kernel<{args.variant}>", flop_per_pair=FLOP_PER_PAIR,
+                    pairs_per_launch=pairs, avg_launch_ms=round(main_run["force_ms"], 4))
+
+    variants = {}
+    if not args.no_fp64 and args.variant != "fp64":
+        fp = run("fp64", max(1, args.steps // 2), 1)
+        f_tf = FLOP_PER_PAIR * pairs / (fp["force_ms"] * 1e-3) / 1e12
+        variants["fp64"] = dict(value=pairs / (fp["ms_per_step"] * 1e-3), unit="pairs/s",
+                                ms_per_step=round(fp["ms_per_step"], 3), force_ms=round(fp["force_ms"], 3),
+                                achieved_tflops=round(f_tf, 3), frac_fp64_peak=round(f_tf / PEAK_FP64_TFLOPS, 4),
+                                frac_fp32_peak=round(f_tf / PEAK_FP32_TFLOPS, 4), res=fp["res"])
+
+    # accuracy of a sample against the oracle, and the oracle's own rate
+    cpu = None
+    accuracy = None
+    if not args.no_cpu_baseline:
+        import oracle
+        from tests import parity
+        xp, vp = oracle.predict(ti, jm.t, jm.x, jm.v, jm.a2, jm.j6)
+        threads = oracle.max_threads()
+        probe = workloads.active_set(ni, min(ni, 64), seed=1)
+        s = slots[probe]
+        c0 = time.perf_counter()
+        oracle.force(xp, vp, jm.m, jm.index, jm.x[s], jm.v[s], jm.index[s], eps2, h2)
+        rate = len(s) * n / (time.perf_counter() - c0)
+        want = int(min(ni, max(256, args.cpu_seconds * rate / n)))
+        ns = 1 << int(np.floor(np.log2(want)))
+        pick = workloads.active_set(ni, ns, seed=2)
+        s = slots[pick]
+        log(f"[bench] oracle on {ns} i x {n} j with {threads} threads (est {ns * n / rate:.1f} s)")
+        c0 = time.perf_counter()
+        ref = oracle.force(xp, vp, jm.m, jm.index, jm.x[s], jm.v[s], jm.index[s], eps2, h2, conditioning=True)
+        cs = time.perf_counter() - c0
+        cpu_rate = ns * n / cs
+        cpu = dict(value=cpu_rate, unit="pairs/s", gflops=round(cpu_rate * FLOP_PER_PAIR / 1e9, 3),
+                   cores=threads, affinity_cpus=len(os.sched_getaffinity(0)), kind="oracle",
+                   seconds=round(cs, 2),
+                   sample=f"{ns} of the {ni} active i-particles (seeded) against all {n} j-particles; "
+                          f"float64 C oracle, OpenMP over i")
+        accuracy = {}
+        for name, res in [(args.variant, main_run["res"])] + [(k, v["res"]) for k, v in variants.items()]:
+            gpu = dict(acc=res["acc"][pick], jerk=res["jerk"][pick], pot=res["pot"][pick])
+            rep = parity.force_report(gpu, ref)
+            nn = parity.nn_report(res["nnb"][pick], ref["nn_index"], ref["nn_r2"], xp, jm.index, jm.x[s])
+            accuracy[name] = dict(acc_max=rep["acc_max"], jerk_max=rep["jerk_max"], pot_max=rep["pot_max"],
+                                  acc_p999=rep["acc_p999"], jerk_p999=rep["jerk_p999"],
+                                  conditioned=rep["acc_conditioned"] + rep["jerk_conditioned"],
+                                  within_tolerance=rep["ok"], nn_mismatch=nn["mismatch"], nn_ok=nn["ok"],
+                                  sample=int(ns))
+    for v in variants.values():
+        v.pop("res", None)
+
+    line = dict(
+        metric=METRIC, value=value, unit="pairs/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=round(main_run["ms_per_step"], 4), higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="f32" if args.variant != "fp64" else "f64", data="synthetic",
+        gflops=round(value * FLOP_PER_PAIR / 1e9, 1),
+        config=dict(workload=jm.meta["name"] + ("_all_active" if ni == n else f"_ni2^{args.log2ni}"),
+                    n=n, ni=ni, eps2=eps2, h2=h2, ti=ti, variant=args.variant,
+                    neighbour_lists=not args.no_neighbour_lists, shape=main_run["shape"],
+                    parallelism="single-gpu"),
+        kernel_ms=dict(predict=round(main_run["predict_ms"], 4), force=round(main_run["force_ms"], 4),
+                       reduce=round(main_run["reduce_ms"], 4)),
+        roofline=roofline, variants=variants, accuracy=accuracy, cpu_baseline=cpu,
+        device=dict(compute_units=info["compute_units"], clock_mhz=info["clock_mhz"],
+                    name=torch.cuda.get_device_name(0)),
+    )
+    g6.g6_close(hid)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,286 @@
+/*
+ * g6mi.h -- C ABI of libg6mi, a direct-summation gravitational force library
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * For a block of active "i-particles" (the sinks) the library computes,
+ * against all "j-particles" (the sources) held in a j-particle memory that
+ * it first predicts to the current time, the Plummer-softened Newtonian
+ *   acceleration  a_i = sum_j m_j r_ij / (r_ij^2 + eps^2)^{3/2}
+ *   jerk          da_i/dt = sum_j m_j [ w_ij / s^{3/2} - 3 (r_ij.w_ij) r_ij / s^{5/2} ]
+ *   potential     phi_i = - sum_j m_j / (r_ij^2 + eps^2)^{1/2}
+ * (r_ij = x_j - x_i, w_ij = v_j - v_i, s = r_ij^2 + eps^2, G = 1), the
+ * nearest neighbour and the neighbour list of each i-particle.  These are
+ * the quantities a 4th-order Hermite integrator with block time steps needs
+ * from its force step (Gaburov, Harfst & Portegies Zwart 2009, "SAPPORO",
+ * Sec. 2 and 2.1); the integrator itself (i-prediction, corrector, time
+ * steps) stays with the caller, as in the paper's CPU/GPU split (Sec. 2.1).
+ *
+ * The g6_* functions follow the GRAPE-6 calling sequence that the paper's
+ * library reproduces so that existing GRAPE-6 clients only relink (Sec. 2.5):
+ *   g6_open -> g6_set_j_particle (for every corrected particle) -> g6_set_ti
+ *   -> g6calc_firsthalf -> [host work] -> g6calc_lasthalf[2]
+ *   -> g6_nearest_neighbour / g6_read_neighbour_list -> g6_get_neighbour_list
+ * Each also has a Fortran alias (trailing underscore, arguments by address).
+ * The g6mi_* functions are extensions: precision variant, launch-shape
+ * control, kernel timing and a device-resident path that takes device
+ * pointers and a HIP stream.
+ *
+ * Conventions shared by every function
+ *   - Positions, velocities, times and masses are float64 in the client's
+ *     units with G = 1.  Arrays declared `double x[][3]` are C row-major,
+ *     three consecutive doubles per particle.
+ *   - `id` is a handle ("cluster id" in GRAPE-6 terms) in [0, G6MI_MAX_HANDLES);
+ *     each open handle owns one independent j-memory on the GPU.
+ *   - The caller owns every host array it passes; the library copies what it
+ *     needs before returning, so arrays may be reused at once.  The library
+ *     owns all GPU memory it allocates.  In the device-resident calls the
+ *     caller owns the device buffers it passes and must keep them alive until
+ *     the work enqueued on `stream` has completed.
+ *   - Nothing aborts or exits.  Functions returning int return 0 on success,
+ *     1 for the documented warnings (non-finite output, neighbour-list
+ *     overflow), or a negative G6MI_E* code; g6mi_last_error(id) gives text.
+ *   - One host thread per handle.  Different handles may be driven from
+ *     different threads.
+ */
+#ifndef G6MI_H
+#define G6MI_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ constants */
+
+/* Maximum neighbours stored per i-particle (Sec. 4: fixed at build time,
+ * default 256). */
+#define G6MI_NB_MAX 256
+/* Default i-particles per call reported by g6_npipes() (Sec. 2.5, footnote:
+ * 256 pipelines).  Larger blocks are accepted up to G6MI_NI_MAX. */
+#define G6MI_NPIPES_DEFAULT 256
+#define G6MI_NI_MAX (1 << 24)
+#define G6MI_NJ_MAX (1 << 26)
+#define G6MI_MAX_HANDLES 16
+
+/* Precision variants of the pair interaction (Sec. 2.2-2.3). */
+#define G6MI_PREC_FP32 0 /* float32 positions and arithmetic                */
+#define G6MI_PREC_DS   1 /* double-single positions, separation by Eq. (3),
+                            float32 arithmetic (the paper's scheme); default */
+#define G6MI_PREC_FP64 2 /* float64 throughout                              */
+
+/* Return codes. */
+#define G6MI_OK          0
+#define G6MI_WARN        1  /* non-finite output, or neighbour-list overflow */
+#define G6MI_EINVAL    (-1) /* bad argument, or arguments of lasthalf differ
+                               from those of the matching firsthalf          */
+#define G6MI_ESTATE    (-2) /* handle not open, or call out of sequence      */
+#define G6MI_EDEVICE   (-3) /* no usable GPU, or a HIP runtime error         */
+#define G6MI_ENOMEM    (-4) /* GPU or pinned host allocation failed          */
+
+/* ------------------------------------------------- GRAPE-6 calling sequence */
+
+/* Create the state of handle `id` on the current HIP device (or the device
+ * named by the environment variable G6MI_DEVICE): stream, j-memory and
+ * work buffers.  Returns 0, G6MI_EINVAL for a bad id, G6MI_ESTATE if the
+ * handle is already open, G6MI_EDEVICE if no GPU is present, G6MI_ENOMEM. */
+int g6_open(int id);
+
+/* Release everything handle `id` holds.  Returns 0 or G6MI_ESTATE. */
+int g6_close(int id);
+
+/* Number of i-particles a GRAPE-6 client should pass per call: 256, or the
+ * value of the environment variable G6MI_NPIPES (1 .. G6MI_NI_MAX). */
+int g6_npipes(void);
+
+/* GRAPE-6 fixed-point scale hints.  Accepted and ignored: the library holds
+ * positions and times in floating point. */
+void g6_set_tunit(int newtunit);
+void g6_set_xunit(int newxunit);
+
+/* Store particle `index` in j-memory slot `address` (0 <= address <
+ * G6MI_NJ_MAX; the memory grows as needed).  `tj` is the time of its last
+ * correction, `mass` its mass, and `x`, `v`, `a2` = a/2, `j6` = jerk/6 its
+ * position, velocity and pre-scaled Taylor coefficients at tj, from which
+ * it is predicted by Eq. (1) and (2) of Sec. 2.2.  `dtj` (its time step)
+ * and `k18` (GRAPE-6's snap term) are accepted and ignored: the predictor
+ * stops at the jerk term.  The record is staged on the host and uploaded by
+ * the next g6calc_firsthalf.  Particle indices must be unique among the slots
+ * used by a calculation; slot `address` is excluded from the forces on the
+ * i-particle with the same index.  Returns 0, G6MI_EINVAL or G6MI_ESTATE. */
+int g6_set_j_particle(int id, int address, int index, double tj, double dtj,
+                      double mass, const double k18[3], const double j6[3],
+                      const double a2[3], const double v[3], const double x[3]);
+
+/* Set the time t_i to which the next calculation predicts the j-particles
+ * (tau_j = t_i - t_j in Eq. (1)-(2)). */
+void g6_set_ti(int id, double ti);
+
+/* Start a force calculation: upload staged j-records, predict j-slots
+ * 0..nj-1 to t_i and compute the forces on the ni i-particles with
+ * particle indices `index`, host-predicted positions `xi` and velocities
+ * `vi`, softening eps2 (one value for the whole block, Sec. 2.5) and
+ * neighbour radii squared h2[i] (a j-particle is a neighbour when its
+ * unsoftened squared distance is strictly below h2[i]).  `aold`, `j6old`
+ * and `phiold` are GRAPE-6 scaling hints and are ignored (may be NULL).
+ * Work is enqueued on the handle's stream and the call returns without
+ * waiting.  Returns 0, G6MI_EINVAL (e.g. nj larger than the slots set, ni
+ * outside 0..G6MI_NI_MAX, non-finite eps2), G6MI_ESTATE, G6MI_EDEVICE or
+ * G6MI_ENOMEM; the error is also returned by the following lasthalf. */
+int g6calc_firsthalf(int id, int nj, int ni, const int index[],
+                     const double xi[][3], const double vi[][3],
+                     const double aold[][3], const double j6old[][3],
+                     const double phiold[], double eps2, const double h2[]);
+
+/* Wait for the calculation started by g6calc_firsthalf and write the
+ * accelerations, jerks and potentials of its ni i-particles.  nj, ni,
+ * index and eps2 must equal those of the firsthalf (G6MI_EINVAL otherwise);
+ * xi, vi and h2 are not read again.  Returns 0, 1 if any output is not
+ * finite (e.g. eps2 = 0 with two distinct particles at the same position),
+ * or a negative error code. */
+int g6calc_lasthalf(int id, int nj, int ni, const int index[],
+                    const double xi[][3], const double vi[][3], double eps2,
+                    const double h2[], double acc[][3], double jerk[][3],
+                    double pot[]);
+
+/* As g6calc_lasthalf, and also write the particle index of each
+ * i-particle's nearest neighbour (-1 if there is no other j-particle). */
+int g6calc_lasthalf2(int id, int nj, int ni, const int index[],
+                     const double xi[][3], const double vi[][3], double eps2,
+                     const double h2[], double acc[][3], double jerk[][3],
+                     double pot[], int nnbindex[]);
+
+/* Nearest neighbour of each of the ni i-particles of the last completed
+ * calculation: particle index and unsoftened squared distance (-1 and
+ * +infinity if none).  The nearest neighbour minimises the squared distance
+ * as computed in the active precision variant; ties go to the lower slot.
+ * Returns 0, G6MI_EINVAL (ni differs from the last calculation) or
+ * G6MI_ESTATE. */
+int g6_nearest_neighbour(int id, int ni, int nnbindex[], double r2nn[]);
+
+/* Copy the neighbour lists of the last completed calculation to the host.
+ * Returns 0, 1 if any i-particle had more than G6MI_NB_MAX neighbours, or a
+ * negative error code. */
+int g6_read_neighbour_list(int id);
+
+/* Neighbour list of i-particle `ipipe` (0-based position in the last
+ * calculation's i-block): particle indices in ascending order.  Writes
+ * *nblen = the true number of neighbours and the first
+ * min(*nblen, maxlength, G6MI_NB_MAX) indices to nbl.  Returns 0, 1 if the
+ * list was cut by maxlength or G6MI_NB_MAX, or a negative error code
+ * (G6MI_ESTATE if g6_read_neighbour_list was not called after the
+ * calculation).  When a list overflowed G6MI_NB_MAX, which G6MI_NB_MAX of
+ * the neighbours are stored is not specified. */
+int g6_get_neighbour_list(int id, int ipipe, int maxlength, int *nblen,
+                          int nbl[]);
+
+/* ------------------------------------------------------------ extensions */
+
+/* Text of the last error on handle id (or of the last global error when
+ * the id is invalid).  The pointer stays valid until the next call on id. */
+const char *g6mi_last_error(int id);
+
+/* G6MI_NB_MAX, for callers that load the library dynamically. */
+int g6mi_nb_max(void);
+
+/* Select the precision variant (G6MI_PREC_*) for subsequent calculations.
+ * The default is G6MI_PREC_DS, or the environment variable G6MI_PRECISION
+ * ("fp32", "ds", "fp64") read at g6_open.  Returns 0, G6MI_EINVAL,
+ * G6MI_ESTATE. */
+int g6mi_set_precision(int id, int prec);
+int g6mi_get_precision(int id);
+
+/* Enable (1, default) or disable (0) neighbour-list construction.  With
+ * lists disabled the neighbour-list calls report zero neighbours (the
+ * paper's build-time switch, Sec. 4).  The nearest neighbour is always
+ * computed.  Returns 0 or a negative code. */
+int g6mi_set_neighbour_lists(int id, int on);
+
+/* Override the launch shape of the interaction kernel: i-particles per
+ * workgroup (a power of two, 1..256) and number of j-splits (1..4096).
+ * 0 restores the automatic choice.  Returns 0 or G6MI_EINVAL. */
+int g6mi_set_shape(int id, int i_per_group, int j_splits);
+
+/* Launch shape used by the last calculation: i per workgroup, j-splits,
+ * j per tile, workgroups.  Returns 0 or a negative code. */
+int g6mi_get_shape(int id, int shape[4]);
+
+/* Enable (1) or disable (0, default) per-kernel timing with HIP events
+ * recorded on the launch stream around the predictor, the interaction
+ * kernel and the reduction of each calculation (up to 4096 calculations are
+ * recorded; enabling again clears the record).  g6mi_last_timing waits for
+ * the last timed calculation and writes its kernel times in milliseconds:
+ * ms[0] predictor, ms[1] interaction, ms[2] reduction.  g6mi_timing_totals
+ * waits for all recorded calculations, writes the sums of their kernel times
+ * and their number, and clears the record.  Returns 0 or a negative code. */
+int g6mi_enable_timing(int id, int on);
+int g6mi_last_timing(int id, double ms[3]);
+int g6mi_timing_totals(int id, double ms[3], int *count);
+
+/* Device-resident path.
+ *
+ * g6mi_set_j_particles_device copies nj j-records from device memory into
+ * slots 0..nj-1 of handle id's j-memory: t[nj], mass[nj], index[nj] and
+ * row-major [nj][3] x, v, a2 (= a/2) and j6 (= jerk/6), all float64 except
+ * index.  The copy is enqueued on `stream` (a hipStream_t; NULL means the
+ * handle's own stream) and the handle's host-side index map is refreshed,
+ * which synchronises that stream.  Returns 0 or a negative code.
+ *
+ * g6mi_calc_device predicts j-slots 0..nj-1 to the time set by g6_set_ti and
+ * computes the forces on ni i-particles whose data are in device memory:
+ * d_islot[i] is the j-slot that holds i-particle i itself (excluded from its
+ * sums) or -1; d_xi, d_vi are [ni][3], d_h2 is [ni].  Outputs d_acc, d_jerk
+ * ([ni][3]) and d_pot, d_nnb (particle index of the nearest neighbour or -1)
+ * and d_r2nn ([ni]) are written in device memory; d_nnb and d_r2nn may be
+ * NULL.  Neighbour lists stay in the handle and are read with
+ * g6_read_neighbour_list / g6_get_neighbour_list.  All work is enqueued on
+ * `stream` without any host synchronisation.  Returns 0 or a negative code
+ * (argument errors are detected before anything is enqueued). */
+int g6mi_set_j_particles_device(int id, int nj, const double *d_t,
+                                const double *d_mass, const int *d_index,
+                                const double *d_x, const double *d_v,
+                                const double *d_a2, const double *d_j6,
+                                void *stream);
+
+int g6mi_calc_device(int id, int nj, int ni, const int *d_islot,
+                     const double *d_xi, const double *d_vi, double eps2,
+                     const double *d_h2, double *d_acc, double *d_jerk,
+                     double *d_pot, int *d_nnb, double *d_r2nn, void *stream);
+
+/* Device properties used by the launch heuristics: compute units and peak
+ * engine clock in MHz.  Returns 0 or a negative code. */
+int g6mi_device_info(int id, int info[2]);
+
+/* ------------------------------------------------------ Fortran aliases */
+int g6_open_(const int *id);
+int g6_close_(const int *id);
+int g6_npipes_(void);
+void g6_set_tunit_(const int *newtunit);
+void g6_set_xunit_(const int *newxunit);
+void g6_set_ti_(const int *id, const double *ti);
+int g6_set_j_particle_(const int *id, const int *address, const int *index,
+                       const double *tj, const double *dtj, const double *mass,
+                       const double k18[3], const double j6[3],
+                       const double a2[3], const double v[3], const double x[3]);
+int g6calc_firsthalf_(const int *id, const int *nj, const int *ni,
+                      const int index[], const double xi[][3],
+                      const double vi[][3], const double aold[][3],
+                      const double j6old[][3], const double phiold[],
+                      const double *eps2, const double h2[]);
+int g6calc_lasthalf_(const int *id, const int *nj, const int *ni,
+                     const int index[], const double xi[][3],
+                     const double vi[][3], const double *eps2,
+                     const double h2[], double acc[][3], double jerk[][3],
+                     double pot[]);
+int g6calc_lasthalf2_(const int *id, const int *nj, const int *ni,
+                      const int index[], const double xi[][3],
+                      const double vi[][3], const double *eps2,
+                      const double h2[], double acc[][3], double jerk[][3],
+                      double pot[], int nnbindex[]);
+int g6_read_neighbour_list_(const int *id);
+int g6_get_neighbour_list_(const int *id, const int *ipipe,
+                           const int *maxlength, int *nblen, int nbl[]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* G6MI_H */

@@ -42,7 +42,7 @@ def _lib():
         lib.oracle_predict.restype = None
         lib.oracle_force.argtypes = [ctypes.c_int64, dp, dp, dp, ip,
                                      ctypes.c_int64, dp, dp, ip, ctypes.c_double, dp,
-                                     ctypes.c_int, dp, dp, dp, ip, dp, lp, ip]
+                                     ctypes.c_int, dp, dp, dp, ip, dp, lp, ip, dp, dp]
         lib.oracle_force.restype = ctypes.c_int64
         lib.oracle_max_threads.restype = ctypes.c_int
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
@@ -85,9 +85,12 @@ def predict(ti, t, x, v, a2, j6):
     return xp, vp
 
 
-def force(xj, vj, mj, jindex, xi, vi, iindex, eps2, h2=None, nb_cap=NB_CAP_DEFAULT):
+def force(xj, vj, mj, jindex, xi, vi, iindex, eps2, h2=None, nb_cap=NB_CAP_DEFAULT,
+          conditioning=False):
     """Force evaluation of i-particles (xi, vi, iindex) by j-particles
-    (xj, vj, mj, jindex).  Returns a dict of float64/int arrays."""
+    (xj, vj, mj, jindex).  Returns a dict of float64/int arrays; with
+    ``conditioning`` also acc_abs / jerk_abs, the sums of the magnitudes of
+    the pair terms."""
     mj = np.ascontiguousarray(mj, dtype=np.float64)
     nj = mj.shape[0]
     iindex = np.ascontiguousarray(iindex, dtype=np.int32)
@@ -104,22 +107,25 @@ def force(xj, vj, mj, jindex, xi, vi, iindex, eps2, h2=None, nb_cap=NB_CAP_DEFAU
         nb_count=np.empty(ni, dtype=np.int64),
         nb_list=np.empty((ni, max(nb_cap, 0)), dtype=np.int32),
     )
+    if conditioning:
+        out["acc_abs"], out["jerk_abs"] = np.empty(ni), np.empty(ni)
     ndeg = _lib().oracle_force(
         nj, _d(xj), _d(vj), _d(mj), _i(jindex), ni, _d(xi), _d(vi), _i(iindex),
         float(eps2), _d(h2), int(nb_cap), _d(out["acc"]), _d(out["jerk"]), _d(out["pot"]),
-        _i(out["nn_index"]), _d(out["nn_r2"]), _l(out["nb_count"]), _i(out["nb_list"]))
+        _i(out["nn_index"]), _d(out["nn_r2"]), _l(out["nb_count"]), _i(out["nb_list"]),
+        _d(out["acc_abs"]) if conditioning else None, _d(out["jerk_abs"]) if conditioning else None)
     out["n_degenerate"] = int(ndeg)
     return out
 
 
-def evaluate(jm, ti, slots, eps2, h2=None, nb_cap=NB_CAP_DEFAULT):
+def evaluate(jm, ti, slots, eps2, h2=None, nb_cap=NB_CAP_DEFAULT, conditioning=False):
     """One block step's force evaluation on a j-memory (``workloads.JMemory``):
     every j-slot is predicted to ti, the active ``slots`` take their predicted
     state as i-particles, and their forces are summed over all other slots."""
     xp, vp = predict(ti, jm.t, jm.x, jm.v, jm.a2, jm.j6)
     slots = np.asarray(slots, dtype=np.int64)
     res = force(xp, vp, jm.m, jm.index, xp[slots], vp[slots], jm.index[slots],
-                eps2, h2, nb_cap)
+                eps2, h2, nb_cap, conditioning)
     res["xi"], res["vi"] = xp[slots], vp[slots]
     return res
 

@@ -107,6 +107,10 @@ static int cmp_int(const void *a, const void *b)
  * first min(count, nb_cap) of them in row i (row length nb_cap), the rest of
  * the row is -1.
  *
+ * Optional outputs acc_abs[i] = sum_k |m_k r / s^{3/2}| and jerk_abs[i] =
+ * sum_k |jerk term of pair k| (NULL to skip) measure how much the sums
+ * cancel: |acc_i| / acc_abs[i] is 1 when all pair forces are parallel.
+ *
  * Returns the number of degenerate pairs.
  */
 int64_t oracle_force(int64_t nj, const double *xj, const double *vj,
@@ -116,7 +120,8 @@ int64_t oracle_force(int64_t nj, const double *xj, const double *vj,
                      int nb_cap,
                      double *acc, double *jerk, double *pot,
                      int *nn_index, double *nn_r2,
-                     int64_t *nb_count, int *nb_list)
+                     int64_t *nb_count, int *nb_list,
+                     double *acc_abs, double *jerk_abs)
 {
     int64_t degenerate = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : degenerate)
@@ -124,6 +129,7 @@ int64_t oracle_force(int64_t nj, const double *xj, const double *vj,
         double ax = 0.0, ay = 0.0, az = 0.0;
         double jx = 0.0, jy = 0.0, jz = 0.0;
         double phi = 0.0;
+        double sa = 0.0, sj = 0.0;
         double best_r2 = INFINITY;
         int best_idx = -1;
         int64_t count = 0, cap = 16;
@@ -173,6 +179,13 @@ int64_t oracle_force(int64_t nj, const double *xj, const double *vj,
             jy += m * (q3 * wy - 3.0 * rw * q3 * q2 * ry);
             jz += m * (q3 * wz - 3.0 * rw * q3 * q2 * rz);
             phi -= m * q;
+            if (acc_abs || jerk_abs) {
+                double ex = m * (q3 * wx - 3.0 * rw * q3 * q2 * rx);
+                double ey = m * (q3 * wy - 3.0 * rw * q3 * q2 * ry);
+                double ez = m * (q3 * wz - 3.0 * rw * q3 * q2 * rz);
+                sa += fabs(m) * q3 * sqrt(r2u);
+                sj += sqrt(ex * ex + ey * ey + ez * ez);
+            }
         }
 
         acc[3 * i + 0] = ax;
@@ -182,6 +195,8 @@ int64_t oracle_force(int64_t nj, const double *xj, const double *vj,
         jerk[3 * i + 1] = jy;
         jerk[3 * i + 2] = jz;
         pot[i] = phi;
+        if (acc_abs) acc_abs[i] = sa;
+        if (jerk_abs) jerk_abs[i] = sj;
         if (nn_index) nn_index[i] = best_idx;
         if (nn_r2) nn_r2[i] = best_r2;
         if (nb_count) nb_count[i] = count;

@@ -1,0 +1,884 @@
+// Host side of libg6mi: handle state, j-memory staging, launch-shape choice
+// and the exported C ABI declared in include/g6mi.h.
+//
+// One calculation enqueues, in order on one HIP stream:
+//   [H2D of staged j-records + scatter kernel]   (only slots changed since
+//                                                  the last calculation)
+//   [H2D of the i-block]                          (host path only)
+//   predict_kernel -> force_kernel -> reduce_kernel
+//   [D2H of the results]                          (host path only)
+// which is the CPU/GPU split of Sec. 2.1: the j-particles are predicted on
+// the GPU, and only corrected particles and the i-block cross the bus.
+
+#include "g6mi_internal.h"
+#include "../../include/g6mi.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#define G6MI_API extern "C" __attribute__((visibility("default")))
+
+namespace {
+
+using namespace g6mi;
+
+constexpr int kRecDoubles = 16; // staged j-record: t m x3 v3 a2(3) j6(3) index pad
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+struct PinBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+size_t round_up(size_t n, size_t q) { return (n + q - 1) / q * q; }
+
+hipError_t ensure(DevBuf &b, size_t bytes) {
+  if (b.bytes >= bytes && b.p) return hipSuccess;
+  b.release();
+  const size_t nb = round_up(std::max<size_t>(bytes, 256), size_t(1) << 16);
+  hipError_t e = hipMalloc(&b.p, nb);
+  if (e == hipSuccess) b.bytes = nb;
+  else b.p = nullptr;
+  return e;
+}
+
+hipError_t ensure(PinBuf &b, size_t bytes) {
+  if (b.bytes >= bytes && b.p) return hipSuccess;
+  b.release();
+  const size_t nb = round_up(std::max<size_t>(bytes, 256), size_t(1) << 16);
+  hipError_t e = hipHostMalloc(&b.p, nb, hipHostMallocDefault);
+  if (e == hipSuccess) b.bytes = nb;
+  else b.p = nullptr;
+  return e;
+}
+
+struct Handle {
+  bool open = false;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int ncu = 0, clock_mhz = 0;
+  int prec = G6MI_PREC_DS;
+  bool nbl = true;
+  int user_ipw = 0, user_nsplit = 0;
+  int shape[4] = {0, 0, 0, 0};
+  std::string err;
+
+  // host master copy of the j-memory, kRecDoubles per slot
+  std::vector<double> h_rec;
+  std::vector<int> h_index;
+  std::vector<unsigned char> h_set, h_dirty;
+  std::vector<int> dirty;
+  size_t n_contig = 0; // slots 0..n_contig-1 have all been set
+  std::unordered_map<int, int> slot_of;
+  double ti = 0.0;
+
+  // device j-memory
+  JMem jm;
+  DevBuf d_jm, d_pred, d_stage;
+  PinBuf h_stage;
+  hipEvent_t stage_ev = nullptr;
+  bool stage_busy = false;
+
+  // host-path i-block and outputs
+  DevBuf d_i, d_out;
+  PinBuf h_i, h_out;
+
+  // work buffers
+  DevBuf d_part, d_nnr2, d_nnslot, d_nbcount, d_nblist, d_flags;
+
+  // calculation state
+  bool pending = false;
+  int pending_err = 0;
+  int c_nj = 0, c_ni = 0;
+  double c_eps2 = 0.0;
+  std::vector<int> c_index;
+  hipStream_t c_stream = nullptr;
+  bool c_have = false;     // a calculation was enqueued and not superseded
+  bool res_valid = false;  // host results of the last host-path calc
+  std::vector<int> r_nnb;
+  std::vector<double> r_r2nn;
+  bool nb_read = false;
+  std::vector<int> r_nbcount, r_nblist;
+
+  // timing: one set of four events per timed calculation since the last
+  // g6mi_enable_timing / g6mi_timing_totals, at most kTimingRing sets
+  bool timing = false;
+  int n_timed = 0;
+  std::vector<std::array<hipEvent_t, 4>> evs;
+};
+
+constexpr int kTimingRing = 4096;
+
+Handle g_h[G6MI_MAX_HANDLES];
+std::mutex g_mu;
+std::string g_err;
+
+int fail(Handle *h, int code, const std::string &msg) {
+  if (h) h->err = msg;
+  else g_err = msg;
+  return code;
+}
+
+int hip_fail(Handle *h, hipError_t e, const char *what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(h, e == hipErrorOutOfMemory ? G6MI_ENOMEM : G6MI_EDEVICE, m);
+}
+
+#define HIPCHK(h, call)                                                        \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) return hip_fail((h), e_, #call);                     \
+  } while (0)
+
+Handle *get_open(int id) {
+  if (id < 0 || id >= G6MI_MAX_HANDLES) {
+    g_err = "invalid handle id";
+    return nullptr;
+  }
+  Handle *h = &g_h[id];
+  if (!h->open) {
+    h->err = "handle not open";
+    return nullptr;
+  }
+  return h;
+}
+
+int code_for_missing(int id) {
+  return (id < 0 || id >= G6MI_MAX_HANDLES) ? G6MI_EINVAL : G6MI_ESTATE;
+}
+
+int parse_precision(const char *s, int dflt) {
+  if (!s) return dflt;
+  std::string v(s);
+  std::transform(v.begin(), v.end(), v.begin(), ::tolower);
+  if (v == "fp32" || v == "sp") return G6MI_PREC_FP32;
+  if (v == "ds") return G6MI_PREC_DS;
+  if (v == "fp64" || v == "dp") return G6MI_PREC_FP64;
+  return dflt;
+}
+
+void grow_host(Handle &h, size_t need) {
+  if (h.h_index.size() >= need) return;
+  size_t n = std::max<size_t>(1024, h.h_index.size());
+  while (n < need) n *= 2;
+  h.h_rec.resize(n * kRecDoubles, 0.0);
+  h.h_index.resize(n, -1);
+  h.h_set.resize(n, 0);
+  h.h_dirty.resize(n, 0);
+}
+
+void mark_dirty(Handle &h, int slot) {
+  if (!h.h_dirty[slot]) {
+    h.h_dirty[slot] = 1;
+    h.dirty.push_back(slot);
+  }
+}
+
+// Device j-memory with room for `need` slots.  A reallocation re-uploads
+// every set slot from the host master copy.
+int ensure_jmem(Handle &h, size_t need) {
+  if (need <= h.jm.cap && h.jm.t) return 0;
+  size_t cap = std::max<size_t>(4096, h.jm.cap);
+  while (cap < need) cap *= 2;
+  HIPCHK(&h, hipStreamSynchronize(h.stream));
+  h.d_jm.release();
+  h.jm = JMem{};
+  const size_t bytes = cap * (14 * sizeof(double) + sizeof(int));
+  HIPCHK(&h, ensure(h.d_jm, bytes));
+  double *b = static_cast<double *>(h.d_jm.p);
+  h.jm.t = b;
+  h.jm.m = b + cap;
+  h.jm.x = b + 2 * cap;
+  h.jm.v = b + 5 * cap;
+  h.jm.a2 = b + 8 * cap;
+  h.jm.j6 = b + 11 * cap;
+  h.jm.index = reinterpret_cast<int *>(b + 14 * cap);
+  h.jm.cap = cap;
+  HIPCHK(&h, hipMemsetAsync(h.d_jm.p, 0, bytes, h.stream));
+  for (size_t k = 0; k < std::min(h.h_set.size(), cap); ++k)
+    if (h.h_set[k]) mark_dirty(h, static_cast<int>(k));
+  return 0;
+}
+
+// Upload the staged j-records on stream s: pack them into pinned memory, one
+// H2D copy, then a scatter kernel into the structure-of-arrays master.
+int upload_dirty(Handle &h, hipStream_t s) {
+  if (h.dirty.empty()) return 0;
+  const size_t nd = h.dirty.size();
+  if (h.stage_busy) {
+    HIPCHK(&h, hipEventSynchronize(h.stage_ev));
+    h.stage_busy = false;
+  }
+  const size_t rec_bytes = nd * kRecDoubles * sizeof(double);
+  const size_t bytes = rec_bytes + nd * sizeof(int);
+  HIPCHK(&h, ensure(h.h_stage, bytes));
+  HIPCHK(&h, ensure(h.d_stage, bytes));
+  double *rec = static_cast<double *>(h.h_stage.p);
+  int *slots = reinterpret_cast<int *>(static_cast<char *>(h.h_stage.p) + rec_bytes);
+  for (size_t q = 0; q < nd; ++q) {
+    const int k = h.dirty[q];
+    std::memcpy(rec + q * kRecDoubles, &h.h_rec[static_cast<size_t>(k) * kRecDoubles],
+                kRecDoubles * sizeof(double));
+    slots[q] = k;
+    h.h_dirty[k] = 0;
+  }
+  h.dirty.clear();
+  HIPCHK(&h, hipMemcpyAsync(h.d_stage.p, h.h_stage.p, bytes, hipMemcpyHostToDevice, s));
+  const double *drec = static_cast<const double *>(h.d_stage.p);
+  const int *dslots = reinterpret_cast<const int *>(static_cast<char *>(h.d_stage.p) + rec_bytes);
+  HIPCHK(&h, launch_scatter(static_cast<int>(nd), dslots, drec, h.jm, s));
+  HIPCHK(&h, hipEventRecord(h.stage_ev, s));
+  h.stage_busy = true;
+  return 0;
+}
+
+int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+// Launch shape.  i-particles per workgroup: the smallest power of two
+// covering the block, at most 256 (one i per lane); below 256 the spare
+// lanes split the j-tile among themselves (Sec. 2.3, Fig. accMP1).
+// j-splits: enough workgroups for ~4 per compute unit (Sec. 2.3, Fig. accGPU
+// splits j over all multiprocessors), never more than there are tiles.
+void choose_shape(Handle &h, int ni, int nj, int &ipw, int &nsplit) {
+  const int ntiles = (nj + kTile - 1) / kTile;
+  if (h.user_ipw) ipw = h.user_ipw;
+  else {
+    ipw = kWG;
+    while (ipw > 1 && ipw / 2 >= ni) ipw /= 2;
+  }
+  const long nib = (ni + ipw - 1) / ipw;
+  if (h.user_nsplit) nsplit = h.user_nsplit;
+  else {
+    const long target = 4L * std::max(1, h.ncu);
+    nsplit = static_cast<int>(std::max(1L, (target + nib - 1) / std::max(1L, nib)));
+  }
+  nsplit = std::max(1, std::min(nsplit, std::max(1, ntiles)));
+  nsplit = std::min(nsplit, 4096);
+}
+
+int enqueue_calc(Handle &h, int nj, int ni, const int *d_islot, const double *d_xi,
+                 const double *d_vi, const double *d_h2, double eps2, double *d_acc,
+                 double *d_jerk, double *d_pot, int *d_nnb, double *d_r2nn, hipStream_t s) {
+  int rc = upload_dirty(h, s);
+  if (rc) return rc;
+  int ipw, nsplit;
+  choose_shape(h, ni, nj, ipw, nsplit);
+  const size_t n = static_cast<size_t>(std::max(ni, 1));
+  HIPCHK(&h, ensure(h.d_pred, std::max<size_t>(1, nj) * pred_record_bytes(h.prec)));
+  HIPCHK(&h, ensure(h.d_part, static_cast<size_t>(nsplit) * 7 * n * sizeof(double)));
+  HIPCHK(&h, ensure(h.d_nnr2, static_cast<size_t>(nsplit) * n * sizeof(double)));
+  HIPCHK(&h, ensure(h.d_nnslot, static_cast<size_t>(nsplit) * n * sizeof(int)));
+  HIPCHK(&h, ensure(h.d_nbcount, n * sizeof(int)));
+  HIPCHK(&h, ensure(h.d_nblist, n * kNbMax * sizeof(int)));
+  HIPCHK(&h, ensure(h.d_flags, 64));
+  int *flags = static_cast<int *>(h.d_flags.p);
+  HIPCHK(&h, hipMemsetAsync(flags, 0, sizeof(int), s));
+
+  h.shape[0] = ipw;
+  h.shape[1] = nsplit;
+  h.shape[2] = kTile;
+  h.shape[3] = ((ni + ipw - 1) / ipw) * nsplit;
+  hipEvent_t *ev = nullptr;
+  if (h.timing && h.n_timed < kTimingRing) {
+    if (static_cast<size_t>(h.n_timed) == h.evs.size()) {
+      std::array<hipEvent_t, 4> q{};
+      for (auto &e : q) HIPCHK(&h, hipEventCreate(&e));
+      h.evs.push_back(q);
+    }
+    ev = h.evs[h.n_timed].data();
+  }
+  if (ev) HIPCHK(&h, hipEventRecord(ev[0], s));
+  HIPCHK(&h, launch_predict(h.prec, nj, h.ti, h.jm, h.d_pred.p,
+                            static_cast<int *>(h.d_nbcount.p), ni, s));
+  if (ev) HIPCHK(&h, hipEventRecord(ev[1], s));
+  ForceArgs a;
+  a.jpred = h.d_pred.p;
+  a.nj = nj;
+  a.ni = ni;
+  a.xi = d_xi;
+  a.vi = d_vi;
+  a.h2 = d_h2;
+  a.islot = d_islot;
+  a.eps2 = eps2;
+  a.ipw = ipw;
+  a.log2ipw = ilog2(ipw);
+  a.part = static_cast<double *>(h.d_part.p);
+  a.nn_r2 = static_cast<double *>(h.d_nnr2.p);
+  a.nn_slot = static_cast<int *>(h.d_nnslot.p);
+  a.nb_count = static_cast<int *>(h.d_nbcount.p);
+  a.nb_slot = static_cast<int *>(h.d_nblist.p);
+  HIPCHK(&h, launch_force(h.prec, h.nbl, a, nsplit, s));
+  if (ev) HIPCHK(&h, hipEventRecord(ev[2], s));
+  HIPCHK(&h, launch_reduce(nsplit, ni, a.part, a.nn_r2, a.nn_slot, h.jm.index, a.nb_count,
+                           a.nb_slot, h.nbl, d_acc, d_jerk, d_pot, d_nnb, d_r2nn, flags, s));
+  if (ev) {
+    HIPCHK(&h, hipEventRecord(ev[3], s));
+    ++h.n_timed;
+  }
+  h.c_nj = nj;
+  h.c_ni = ni;
+  h.c_eps2 = eps2;
+  h.c_stream = s;
+  h.c_have = true;
+  h.nb_read = false;
+  return 0;
+}
+
+bool finite3(const double *p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
+
+// Layout of the host-path i-block and result buffers (same on both sides).
+struct IBlockLayout {
+  size_t xi, vi, h2, islot, bytes;
+  explicit IBlockLayout(size_t n) {
+    xi = 0;
+    vi = xi + 3 * n * sizeof(double);
+    h2 = vi + 3 * n * sizeof(double);
+    islot = h2 + n * sizeof(double);
+    bytes = islot + n * sizeof(int);
+  }
+};
+struct OutLayout {
+  size_t acc, jerk, pot, r2nn, nnb, flags, bytes;
+  explicit OutLayout(size_t n) {
+    acc = 0;
+    jerk = acc + 3 * n * sizeof(double);
+    pot = jerk + 3 * n * sizeof(double);
+    r2nn = pot + n * sizeof(double);
+    nnb = r2nn + n * sizeof(double);
+    flags = round_up(nnb + n * sizeof(int), 16);
+    bytes = flags + 16;
+  }
+};
+
+int firsthalf_impl(Handle &h, int nj, int ni, const int *index, const double (*xi)[3],
+                   const double (*vi)[3], double eps2, const double *h2) {
+  if (nj < 0 || static_cast<size_t>(nj) > h.n_contig)
+    return fail(&h, G6MI_EINVAL, "nj exceeds the number of j-slots set from slot 0");
+  if (ni < 0 || ni > G6MI_NI_MAX) return fail(&h, G6MI_EINVAL, "ni out of range");
+  if (ni > 0 && (!index || !xi || !vi)) return fail(&h, G6MI_EINVAL, "null i-particle array");
+  if (!std::isfinite(eps2) || eps2 < 0.0) return fail(&h, G6MI_EINVAL, "eps2 must be finite and >= 0");
+  for (int i = 0; i < ni; ++i)
+    if (!finite3(xi[i]) || !finite3(vi[i]) || (h2 && std::isnan(h2[i])))
+      return fail(&h, G6MI_EINVAL, "non-finite i-particle data");
+  int rc = ensure_jmem(h, std::max<size_t>(1, static_cast<size_t>(nj)));
+  if (rc) return rc;
+  const size_t n = static_cast<size_t>(std::max(ni, 1));
+  IBlockLayout il(n);
+  OutLayout ol(n);
+  if (h.stage_busy) { // the i-block shares nothing with the j staging, but
+    HIPCHK(&h, hipEventSynchronize(h.stage_ev)); // keep one staging fence
+    h.stage_busy = false;
+  }
+  HIPCHK(&h, ensure(h.h_i, il.bytes));
+  HIPCHK(&h, ensure(h.d_i, il.bytes));
+  HIPCHK(&h, ensure(h.h_out, ol.bytes));
+  HIPCHK(&h, ensure(h.d_out, ol.bytes));
+  char *hi = static_cast<char *>(h.h_i.p);
+  double *pxi = reinterpret_cast<double *>(hi + il.xi);
+  double *pvi = reinterpret_cast<double *>(hi + il.vi);
+  double *ph2 = reinterpret_cast<double *>(hi + il.h2);
+  int *pis = reinterpret_cast<int *>(hi + il.islot);
+  for (int i = 0; i < ni; ++i) {
+    for (int d = 0; d < 3; ++d) {
+      pxi[3 * i + d] = xi[i][d];
+      pvi[3 * i + d] = vi[i][d];
+    }
+    ph2[i] = h2 ? h2[i] : 0.0;
+    auto it = h.slot_of.find(index[i]);
+    pis[i] = (it != h.slot_of.end() && it->second < nj) ? it->second : -1;
+  }
+  hipStream_t s = h.stream;
+  HIPCHK(&h, hipMemcpyAsync(h.d_i.p, h.h_i.p, il.bytes, hipMemcpyHostToDevice, s));
+  char *di = static_cast<char *>(h.d_i.p);
+  char *dout = static_cast<char *>(h.d_out.p);
+  rc = enqueue_calc(h, nj, ni, reinterpret_cast<const int *>(di + il.islot),
+                    reinterpret_cast<const double *>(di + il.xi),
+                    reinterpret_cast<const double *>(di + il.vi),
+                    reinterpret_cast<const double *>(di + il.h2), eps2,
+                    reinterpret_cast<double *>(dout + ol.acc),
+                    reinterpret_cast<double *>(dout + ol.jerk),
+                    reinterpret_cast<double *>(dout + ol.pot),
+                    reinterpret_cast<int *>(dout + ol.nnb),
+                    reinterpret_cast<double *>(dout + ol.r2nn), s);
+  if (rc) return rc;
+  HIPCHK(&h, hipMemcpyAsync(dout + ol.flags, h.d_flags.p, sizeof(int), hipMemcpyDeviceToDevice, s));
+  HIPCHK(&h, hipMemcpyAsync(h.h_out.p, h.d_out.p, ol.bytes, hipMemcpyDeviceToHost, s));
+  h.c_index.assign(index, index + ni);
+  return 0;
+}
+
+int lasthalf_impl(int id, int nj, int ni, const int *index, double eps2, double (*acc)[3],
+                  double (*jerk)[3], double *pot, int *nnbindex) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  if (!h->pending) return fail(h, G6MI_ESTATE, "g6calc_lasthalf without g6calc_firsthalf");
+  h->pending = false;
+  if (h->pending_err) {
+    h->c_have = false;
+    return h->pending_err;
+  }
+  HIPCHK(h, hipSetDevice(h->device));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (nj != h->c_nj || ni != h->c_ni || eps2 != h->c_eps2 ||
+      (ni > 0 && (!index || std::memcmp(index, h->c_index.data(), sizeof(int) * ni) != 0)))
+    return fail(h, G6MI_EINVAL, "lasthalf arguments differ from firsthalf");
+  if (ni > 0 && (!acc || !jerk || !pot)) return fail(h, G6MI_EINVAL, "null output array");
+  const size_t n = static_cast<size_t>(std::max(ni, 1));
+  OutLayout ol(n);
+  const char *ho = static_cast<const char *>(h->h_out.p);
+  const double *pa = reinterpret_cast<const double *>(ho + ol.acc);
+  const double *pj = reinterpret_cast<const double *>(ho + ol.jerk);
+  const double *pp = reinterpret_cast<const double *>(ho + ol.pot);
+  const double *pr = reinterpret_cast<const double *>(ho + ol.r2nn);
+  const int *pn = reinterpret_cast<const int *>(ho + ol.nnb);
+  const int flags = *reinterpret_cast<const int *>(ho + ol.flags);
+  for (int i = 0; i < ni; ++i) {
+    for (int d = 0; d < 3; ++d) {
+      acc[i][d] = pa[3 * i + d];
+      jerk[i][d] = pj[3 * i + d];
+    }
+    pot[i] = pp[i];
+    if (nnbindex) nnbindex[i] = pn[i];
+  }
+  h->r_nnb.assign(pn, pn + ni);
+  h->r_r2nn.assign(pr, pr + ni);
+  h->res_valid = true;
+  return (ni > 0 && (flags & 1)) ? G6MI_WARN : G6MI_OK;
+}
+
+} // namespace
+
+// =========================================================== exported ABI
+
+G6MI_API int g6_open(int id) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (id < 0 || id >= G6MI_MAX_HANDLES) return fail(nullptr, G6MI_EINVAL, "invalid handle id");
+  Handle &h = g_h[id];
+  if (h.open) return fail(&h, G6MI_ESTATE, "handle already open");
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return fail(&h, G6MI_EDEVICE, "no HIP device available");
+  }
+  int dev = 0;
+  if (const char *s = std::getenv("G6MI_DEVICE")) dev = std::atoi(s);
+  else if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  if (dev < 0 || dev >= ndev) return fail(&h, G6MI_EDEVICE, "G6MI_DEVICE out of range");
+  h = Handle{};
+  h.device = dev;
+  HIPCHK(&h, hipSetDevice(dev));
+  hipDeviceProp_t prop;
+  HIPCHK(&h, hipGetDeviceProperties(&prop, dev));
+  h.ncu = prop.multiProcessorCount;
+  h.clock_mhz = prop.clockRate / 1000;
+  HIPCHK(&h, hipStreamCreateWithFlags(&h.stream, hipStreamNonBlocking));
+  HIPCHK(&h, hipEventCreateWithFlags(&h.stage_ev, hipEventDisableTiming));
+  h.prec = parse_precision(std::getenv("G6MI_PRECISION"), G6MI_PREC_DS);
+  h.open = true;
+  return G6MI_OK;
+}
+
+G6MI_API int g6_close(int id) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  if (h->c_stream && h->c_stream != h->stream) (void)hipStreamSynchronize(h->c_stream);
+  for (DevBuf *b : {&h->d_jm, &h->d_pred, &h->d_stage, &h->d_i, &h->d_out, &h->d_part,
+                    &h->d_nnr2, &h->d_nnslot, &h->d_nbcount, &h->d_nblist, &h->d_flags})
+    b->release();
+  for (PinBuf *b : {&h->h_stage, &h->h_i, &h->h_out}) b->release();
+  for (auto &q : h->evs)
+    for (auto &ev : q) (void)hipEventDestroy(ev);
+  if (h->stage_ev) (void)hipEventDestroy(h->stage_ev);
+  if (h->stream) (void)hipStreamDestroy(h->stream);
+  *h = Handle{};
+  return G6MI_OK;
+}
+
+G6MI_API int g6_npipes(void) {
+  if (const char *s = std::getenv("G6MI_NPIPES")) {
+    const long v = std::atol(s);
+    if (v >= 1 && v <= G6MI_NI_MAX) return static_cast<int>(v);
+  }
+  return G6MI_NPIPES_DEFAULT;
+}
+
+G6MI_API void g6_set_tunit(int) {}
+G6MI_API void g6_set_xunit(int) {}
+
+G6MI_API int g6_set_j_particle(int id, int address, int index, double tj, double dtj,
+                               double mass, const double k18[3], const double j6[3],
+                               const double a2[3], const double v[3], const double x[3]) {
+  (void)dtj;
+  (void)k18;
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  if (address < 0 || address >= G6MI_NJ_MAX) return fail(h, G6MI_EINVAL, "address out of range");
+  if (!j6 || !a2 || !v || !x) return fail(h, G6MI_EINVAL, "null j-particle array");
+  if (!std::isfinite(tj) || !std::isfinite(mass) || !finite3(x) || !finite3(v) || !finite3(a2) ||
+      !finite3(j6))
+    return fail(h, G6MI_EINVAL, "non-finite j-particle data");
+  grow_host(*h, static_cast<size_t>(address) + 1);
+  double *r = &h->h_rec[static_cast<size_t>(address) * kRecDoubles];
+  r[0] = tj;
+  r[1] = mass;
+  for (int d = 0; d < 3; ++d) {
+    r[2 + d] = x[d];
+    r[5 + d] = v[d];
+    r[8 + d] = a2[d];
+    r[11 + d] = j6[d];
+  }
+  r[14] = static_cast<double>(index);
+  r[15] = 0.0;
+  const int old = h->h_index[address];
+  if (old != index) {
+    auto it = h->slot_of.find(old);
+    if (old >= 0 && it != h->slot_of.end() && it->second == address) h->slot_of.erase(it);
+  }
+  h->h_index[address] = index;
+  h->slot_of[index] = address;
+  h->h_set[address] = 1;
+  while (h->n_contig < h->h_set.size() && h->h_set[h->n_contig]) ++h->n_contig;
+  mark_dirty(*h, address);
+  return G6MI_OK;
+}
+
+G6MI_API void g6_set_ti(int id, double ti) {
+  Handle *h = get_open(id);
+  if (h) h->ti = ti;
+}
+
+G6MI_API int g6calc_firsthalf(int id, int nj, int ni, const int index[], const double xi[][3],
+                              const double vi[][3], const double aold[][3],
+                              const double j6old[][3], const double phiold[], double eps2,
+                              const double h2[]) {
+  (void)aold;
+  (void)j6old;
+  (void)phiold;
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  if (h->pending && !h->pending_err) (void)hipStreamSynchronize(h->stream); // superseded
+  h->pending = true;
+  h->res_valid = false;
+  h->c_have = false;
+  hipError_t e = hipSetDevice(h->device);
+  int rc = e == hipSuccess ? firsthalf_impl(*h, nj, ni, index, xi, vi, eps2, h2)
+                           : hip_fail(h, e, "hipSetDevice");
+  h->pending_err = rc;
+  return rc;
+}
+
+G6MI_API int g6calc_lasthalf(int id, int nj, int ni, const int index[], const double xi[][3],
+                             const double vi[][3], double eps2, const double h2[],
+                             double acc[][3], double jerk[][3], double pot[]) {
+  (void)xi;
+  (void)vi;
+  (void)h2;
+  return lasthalf_impl(id, nj, ni, index, eps2, acc, jerk, pot, nullptr);
+}
+
+G6MI_API int g6calc_lasthalf2(int id, int nj, int ni, const int index[], const double xi[][3],
+                              const double vi[][3], double eps2, const double h2[],
+                              double acc[][3], double jerk[][3], double pot[],
+                              int nnbindex[]) {
+  (void)xi;
+  (void)vi;
+  (void)h2;
+  return lasthalf_impl(id, nj, ni, index, eps2, acc, jerk, pot, nnbindex);
+}
+
+G6MI_API int g6_nearest_neighbour(int id, int ni, int nnbindex[], double r2nn[]) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  if (!h->res_valid) {
+    // device-path calculation: fetch the nearest neighbours from its buffers
+    return fail(h, G6MI_ESTATE, "no completed host-path calculation");
+  }
+  if (ni != h->c_ni) return fail(h, G6MI_EINVAL, "ni differs from the last calculation");
+  for (int i = 0; i < ni; ++i) {
+    if (nnbindex) nnbindex[i] = h->r_nnb[i];
+    if (r2nn) r2nn[i] = h->r_r2nn[i];
+  }
+  return G6MI_OK;
+}
+
+G6MI_API int g6_read_neighbour_list(int id) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  if (!h->c_have || h->pending) return fail(h, G6MI_ESTATE, "no completed calculation");
+  HIPCHK(h, hipSetDevice(h->device));
+  HIPCHK(h, hipStreamSynchronize(h->c_stream));
+  const size_t n = static_cast<size_t>(h->c_ni);
+  h->r_nbcount.assign(n, 0);
+  h->r_nblist.assign(n * kNbMax, -1);
+  if (n > 0) {
+    HIPCHK(h, hipMemcpy(h->r_nbcount.data(), h->d_nbcount.p, n * sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(h, hipMemcpy(h->r_nblist.data(), h->d_nblist.p, n * kNbMax * sizeof(int),
+                        hipMemcpyDeviceToHost));
+  }
+  h->nb_read = true;
+  bool over = false;
+  for (size_t i = 0; i < n; ++i) over = over || h->r_nbcount[i] > kNbMax;
+  return over ? G6MI_WARN : G6MI_OK;
+}
+
+G6MI_API int g6_get_neighbour_list(int id, int ipipe, int maxlength, int *nblen, int nbl[]) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  if (!h->nb_read) return fail(h, G6MI_ESTATE, "g6_read_neighbour_list was not called");
+  if (ipipe < 0 || ipipe >= h->c_ni || maxlength < 0 || !nblen || (maxlength > 0 && !nbl))
+    return fail(h, G6MI_EINVAL, "bad neighbour-list request");
+  const int cnt = h->r_nbcount[ipipe];
+  const int k = std::min(std::min(cnt, maxlength), kNbMax);
+  std::memcpy(nbl, &h->r_nblist[static_cast<size_t>(ipipe) * kNbMax], sizeof(int) * k);
+  *nblen = cnt;
+  return cnt > k ? G6MI_WARN : G6MI_OK;
+}
+
+G6MI_API const char *g6mi_last_error(int id) {
+  if (id < 0 || id >= G6MI_MAX_HANDLES) return g_err.c_str();
+  return g_h[id].err.c_str();
+}
+
+G6MI_API int g6mi_nb_max(void) { return G6MI_NB_MAX; }
+
+G6MI_API int g6mi_set_precision(int id, int prec) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  if (prec != G6MI_PREC_FP32 && prec != G6MI_PREC_DS && prec != G6MI_PREC_FP64)
+    return fail(h, G6MI_EINVAL, "unknown precision variant");
+  h->prec = prec;
+  return G6MI_OK;
+}
+
+G6MI_API int g6mi_get_precision(int id) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  return h->prec;
+}
+
+G6MI_API int g6mi_set_neighbour_lists(int id, int on) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  h->nbl = on != 0;
+  return G6MI_OK;
+}
+
+G6MI_API int g6mi_set_shape(int id, int i_per_group, int j_splits) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  if (i_per_group < 0 || i_per_group > kWG || (i_per_group & (i_per_group - 1)) ||
+      j_splits < 0 || j_splits > 4096)
+    return fail(h, G6MI_EINVAL, "bad launch shape");
+  h->user_ipw = i_per_group;
+  h->user_nsplit = j_splits;
+  return G6MI_OK;
+}
+
+G6MI_API int g6mi_get_shape(int id, int shape[4]) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  if (!shape) return fail(h, G6MI_EINVAL, "null shape");
+  for (int q = 0; q < 4; ++q) shape[q] = h->shape[q];
+  return G6MI_OK;
+}
+
+G6MI_API int g6mi_enable_timing(int id, int on) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  h->timing = on != 0;
+  h->n_timed = 0;
+  return G6MI_OK;
+}
+
+namespace {
+int timing_of(Handle *h, int k, double ms[3]) {
+  HIPCHK(h, hipEventSynchronize(h->evs[k][3]));
+  for (int q = 0; q < 3; ++q) {
+    float t = 0.0f;
+    HIPCHK(h, hipEventElapsedTime(&t, h->evs[k][q], h->evs[k][q + 1]));
+    ms[q] = t;
+  }
+  return 0;
+}
+} // namespace
+
+G6MI_API int g6mi_last_timing(int id, double ms[3]) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  if (!ms) return fail(h, G6MI_EINVAL, "null ms");
+  if (h->n_timed == 0) return fail(h, G6MI_ESTATE, "no timed calculation");
+  HIPCHK(h, hipSetDevice(h->device));
+  return timing_of(h, h->n_timed - 1, ms);
+}
+
+G6MI_API int g6mi_timing_totals(int id, double ms[3], int *count) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  if (!ms || !count) return fail(h, G6MI_EINVAL, "null argument");
+  HIPCHK(h, hipSetDevice(h->device));
+  ms[0] = ms[1] = ms[2] = 0.0;
+  for (int k = 0; k < h->n_timed; ++k) {
+    double one[3];
+    int rc = timing_of(h, k, one);
+    if (rc) return rc;
+    for (int q = 0; q < 3; ++q) ms[q] += one[q];
+  }
+  *count = h->n_timed;
+  h->n_timed = 0;
+  return G6MI_OK;
+}
+
+G6MI_API int g6mi_set_j_particles_device(int id, int nj, const double *d_t, const double *d_mass,
+                                         const int *d_index, const double *d_x,
+                                         const double *d_v, const double *d_a2,
+                                         const double *d_j6, void *stream) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  if (nj < 0 || nj > G6MI_NJ_MAX) return fail(h, G6MI_EINVAL, "nj out of range");
+  if (nj > 0 && (!d_t || !d_mass || !d_index || !d_x || !d_v || !d_a2 || !d_j6))
+    return fail(h, G6MI_EINVAL, "null device array");
+  HIPCHK(h, hipSetDevice(h->device));
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : h->stream;
+  // the host master must stay authoritative: bring it in sync first
+  grow_host(*h, std::max(1, nj));
+  int rc = ensure_jmem(*h, std::max<size_t>(h->h_set.size(), static_cast<size_t>(std::max(nj, 1))));
+  if (rc) return rc;
+  rc = upload_dirty(*h, h->stream);
+  if (rc) return rc;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (s != h->stream) HIPCHK(h, hipStreamSynchronize(s));
+  HIPCHK(h, launch_load(nj, d_t, d_mass, d_index, d_x, d_v, d_a2, d_j6, h->jm, s));
+  // mirror the new records into the host master copy
+  std::vector<double> tmp(static_cast<size_t>(nj) * 3);
+  std::vector<double> col(static_cast<size_t>(nj));
+  std::vector<int> idx(static_cast<size_t>(nj));
+  HIPCHK(h, hipStreamSynchronize(s));
+  if (nj > 0) {
+    HIPCHK(h, hipMemcpy(idx.data(), h->jm.index, sizeof(int) * nj, hipMemcpyDeviceToHost));
+    HIPCHK(h, hipMemcpy(col.data(), h->jm.t, sizeof(double) * nj, hipMemcpyDeviceToHost));
+    for (int k = 0; k < nj; ++k) h->h_rec[static_cast<size_t>(k) * kRecDoubles + 0] = col[k];
+    HIPCHK(h, hipMemcpy(col.data(), h->jm.m, sizeof(double) * nj, hipMemcpyDeviceToHost));
+    for (int k = 0; k < nj; ++k) h->h_rec[static_cast<size_t>(k) * kRecDoubles + 1] = col[k];
+    const double *srcs[4] = {h->jm.x, h->jm.v, h->jm.a2, h->jm.j6};
+    for (int f = 0; f < 4; ++f)
+      for (int d = 0; d < 3; ++d) {
+        HIPCHK(h, hipMemcpy(col.data(), srcs[f] + d * h->jm.cap, sizeof(double) * nj,
+                            hipMemcpyDeviceToHost));
+        for (int k = 0; k < nj; ++k)
+          h->h_rec[static_cast<size_t>(k) * kRecDoubles + 2 + 3 * f + d] = col[k];
+      }
+  }
+  for (int k = 0; k < nj; ++k) {
+    const int old = h->h_index[k];
+    auto it = h->slot_of.find(old);
+    if (old >= 0 && it != h->slot_of.end() && it->second == k) h->slot_of.erase(it);
+  }
+  for (int k = 0; k < nj; ++k) {
+    h->h_rec[static_cast<size_t>(k) * kRecDoubles + 14] = static_cast<double>(idx[k]);
+    h->h_index[k] = idx[k];
+    h->slot_of[idx[k]] = k;
+    h->h_set[k] = 1;
+  }
+  while (h->n_contig < h->h_set.size() && h->h_set[h->n_contig]) ++h->n_contig;
+  return G6MI_OK;
+}
+
+G6MI_API int g6mi_calc_device(int id, int nj, int ni, const int *d_islot, const double *d_xi,
+                              const double *d_vi, double eps2, const double *d_h2,
+                              double *d_acc, double *d_jerk, double *d_pot, int *d_nnb,
+                              double *d_r2nn, void *stream) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  if (h->pending) return fail(h, G6MI_ESTATE, "a host-path calculation is pending");
+  if (nj < 0 || static_cast<size_t>(nj) > h->n_contig)
+    return fail(h, G6MI_EINVAL, "nj exceeds the number of j-slots set from slot 0");
+  if (ni < 0 || ni > G6MI_NI_MAX) return fail(h, G6MI_EINVAL, "ni out of range");
+  if (ni > 0 && (!d_islot || !d_xi || !d_vi || !d_h2 || !d_acc || !d_jerk || !d_pot))
+    return fail(h, G6MI_EINVAL, "null device array");
+  if (!std::isfinite(eps2) || eps2 < 0.0) return fail(h, G6MI_EINVAL, "eps2 must be finite and >= 0");
+  HIPCHK(h, hipSetDevice(h->device));
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : h->stream;
+  int rc = ensure_jmem(*h, std::max<size_t>(1, static_cast<size_t>(nj)));
+  if (rc) return rc;
+  h->res_valid = false;
+  return enqueue_calc(*h, nj, ni, d_islot, d_xi, d_vi, d_h2, eps2, d_acc, d_jerk, d_pot, d_nnb,
+                      d_r2nn, s);
+}
+
+G6MI_API int g6mi_device_info(int id, int info[2]) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  if (!info) return fail(h, G6MI_EINVAL, "null info");
+  info[0] = h->ncu;
+  info[1] = h->clock_mhz;
+  return G6MI_OK;
+}
+
+// ----------------------------------------------------------- Fortran aliases
+G6MI_API int g6_open_(const int *id) { return g6_open(*id); }
+G6MI_API int g6_close_(const int *id) { return g6_close(*id); }
+G6MI_API int g6_npipes_(void) { return g6_npipes(); }
+G6MI_API void g6_set_tunit_(const int *t) { g6_set_tunit(*t); }
+G6MI_API void g6_set_xunit_(const int *x) { g6_set_xunit(*x); }
+G6MI_API void g6_set_ti_(const int *id, const double *ti) { g6_set_ti(*id, *ti); }
+G6MI_API int g6_set_j_particle_(const int *id, const int *address, const int *index,
+                                const double *tj, const double *dtj, const double *mass,
+                                const double k18[3], const double j6[3], const double a2[3],
+                                const double v[3], const double x[3]) {
+  return g6_set_j_particle(*id, *address, *index, *tj, *dtj, *mass, k18, j6, a2, v, x);
+}
+G6MI_API int g6calc_firsthalf_(const int *id, const int *nj, const int *ni, const int index[],
+                               const double xi[][3], const double vi[][3],
+                               const double aold[][3], const double j6old[][3],
+                               const double phiold[], const double *eps2, const double h2[]) {
+  return g6calc_firsthalf(*id, *nj, *ni, index, xi, vi, aold, j6old, phiold, *eps2, h2);
+}
+G6MI_API int g6calc_lasthalf_(const int *id, const int *nj, const int *ni, const int index[],
+                              const double xi[][3], const double vi[][3], const double *eps2,
+                              const double h2[], double acc[][3], double jerk[][3],
+                              double pot[]) {
+  return g6calc_lasthalf(*id, *nj, *ni, index, xi, vi, *eps2, h2, acc, jerk, pot);
+}
+G6MI_API int g6calc_lasthalf2_(const int *id, const int *nj, const int *ni, const int index[],
+                               const double xi[][3], const double vi[][3], const double *eps2,
+                               const double h2[], double acc[][3], double jerk[][3],
+                               double pot[], int nnbindex[]) {
+  return g6calc_lasthalf2(*id, *nj, *ni, index, xi, vi, *eps2, h2, acc, jerk, pot, nnbindex);
+}
+G6MI_API int g6_read_neighbour_list_(const int *id) { return g6_read_neighbour_list(*id); }
+G6MI_API int g6_get_neighbour_list_(const int *id, const int *ipipe, const int *maxlength,
+                                    int *nblen, int nbl[]) {
+  return g6_get_neighbour_list(*id, *ipipe, *maxlength, nblen, nbl);
+}

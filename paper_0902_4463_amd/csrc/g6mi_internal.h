@@ -1,0 +1,75 @@
+// Internal interface between the host-side state machine (g6mi_api.cpp) and
+// the gfx950 kernels (g6mi_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace g6mi {
+
+constexpr int kWG = 256;    // lanes per workgroup: four wave64
+constexpr int kTile = 256;  // j-records staged in LDS per tile
+constexpr int kNbMax = 256; // neighbour slots per i-particle
+
+// Predicted j-record sizes in bytes, one record per j-slot:
+//   DS   : float4{x_hi, m}, float4{x_lo, 0}, float4{v, 0}  = 48 B
+//   FP32 : float4{x, m},    float4{v, 0}                    = 32 B
+//   FP64 : double4{x, m},   double4{v, 0}                   = 64 B
+size_t pred_record_bytes(int prec);
+
+// j-memory master copy on the device: float64 structure of arrays with
+// `cap` slots; x, v, a2, j6 are [3][cap] (component-major) for coalesced
+// predictor loads.
+struct JMem {
+  double *t = nullptr, *m = nullptr;
+  double *x = nullptr, *v = nullptr, *a2 = nullptr, *j6 = nullptr;
+  int *index = nullptr;
+  size_t cap = 0;
+};
+
+struct ForceArgs {
+  const void *jpred = nullptr; // predicted j-records, nj of them
+  int nj = 0;
+  int ni = 0;
+  const double *xi = nullptr;  // [ni][3]
+  const double *vi = nullptr;  // [ni][3]
+  const double *h2 = nullptr;  // [ni]
+  const int *islot = nullptr;  // [ni], own j-slot or -1
+  double eps2 = 0.0;
+  int ipw = kWG;               // i-particles per workgroup, power of two
+  int log2ipw = 8;
+  // outputs of the j-split s in [0, nsplit), component-major:
+  double *part = nullptr;      // [nsplit][7][ni]: acc xyz, jerk xyz, sum m/r
+  double *nn_r2 = nullptr;     // [nsplit][ni]
+  int *nn_slot = nullptr;      // [nsplit][ni]
+  int *nb_count = nullptr;     // [ni]   (zeroed by the predictor launch)
+  int *nb_slot = nullptr;      // [ni][kNbMax]
+};
+
+hipError_t launch_predict(int prec, int nj, double ti, const JMem &jm,
+                          void *out, int *nb_count, int ni, hipStream_t s);
+
+hipError_t launch_force(int prec, bool nbl, const ForceArgs &a, int nsplit,
+                        hipStream_t s);
+
+hipError_t launch_reduce(int nsplit, int ni, const double *part,
+                         const double *nn_r2, const int *nn_slot,
+                         const int *jindex, int *nb_count, int *nb_slot,
+                         bool nbl, double *acc, double *jerk, double *pot,
+                         int *nnb, double *r2nn, int *flags, hipStream_t s);
+
+// Scatter nd staged records into the j-memory.  rec is [nd][16] doubles:
+// t, m, x[3], v[3], a2[3], j6[3], index (as double), pad; slots is [nd].
+hipError_t launch_scatter(int nd, const int *slots, const double *rec,
+                          const JMem &jm, hipStream_t s);
+
+// Copy nj records given as device arrays (row-major [nj][3] vectors) into
+// slots 0..nj-1 of the j-memory.
+hipError_t launch_load(int nj, const double *t, const double *m,
+                       const int *index, const double *x, const double *v,
+                       const double *a2, const double *j6, const JMem &jm,
+                       hipStream_t s);
+
+} // namespace g6mi

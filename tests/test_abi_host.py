@@ -1,0 +1,107 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+the header declares, and reports errors instead of aborting."""
+
+import ctypes
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "g6mi.h")
+GOLDEN = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_constants.json")))
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(g6\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def g6():
+    import paper_0902_4463_amd as g6
+    return g6
+
+
+def test_header_declares_grape_sequence():
+    names = declared_functions()
+    for n in ("g6_open", "g6_close", "g6_npipes", "g6_set_j_particle", "g6_set_ti",
+              "g6calc_firsthalf", "g6calc_lasthalf", "g6calc_lasthalf2", "g6_nearest_neighbour",
+              "g6_read_neighbour_list", "g6_get_neighbour_list", "g6mi_calc_device"):
+        assert n in names
+        assert n + "_" in names or n.startswith("g6mi") or n == "g6_nearest_neighbour"
+
+
+def test_every_declared_symbol_is_exported(g6):
+    lib = ctypes.CDLL(g6.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_c_names(g6):
+    for n in declared_functions():
+        if n.endswith("_") and not n.startswith("g6mi"):
+            continue  # Fortran aliases are for Fortran callers
+        assert hasattr(g6, n), n
+
+
+def test_constants_match_paper(g6):
+    assert g6.g6mi_nb_max() == GOLDEN["neighbour_list_cap"]["value"]
+    assert g6.NB_MAX == g6.g6mi_nb_max()
+    old = os.environ.pop("G6MI_NPIPES", None)
+    try:
+        assert g6.g6_npipes() == GOLDEN["npipes"]["value"]
+        os.environ["G6MI_NPIPES"] = "1048576"
+        assert g6.g6_npipes() == 1048576
+        os.environ["G6MI_NPIPES"] = "0"
+        assert g6.g6_npipes() == GOLDEN["npipes"]["value"]
+    finally:
+        os.environ.pop("G6MI_NPIPES", None)
+        if old is not None:
+            os.environ["G6MI_NPIPES"] = old
+
+
+def test_header_constants_agree_with_binding(g6):
+    text = open(HEADER).read()
+    consts = dict(re.findall(r"#define\s+(G6MI_\w+)\s+\(?(-?\d+)\)?", text))
+    assert int(consts["G6MI_NB_MAX"]) == g6.NB_MAX
+    assert int(consts["G6MI_NPIPES_DEFAULT"]) == g6.NPIPES_DEFAULT
+    assert int(consts["G6MI_PREC_DS"]) == g6.PREC_DS
+    assert int(consts["G6MI_EDEVICE"]) == g6.EDEVICE
+
+
+def test_errors_not_aborts_without_gpu(g6):
+    """In a process that has no GPU, g6_open reports G6MI_EDEVICE and every
+    handle call reports that the handle is not open."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert g6.g6_open(0) == g6.EDEVICE
+    assert "device" in g6.last_error(0)
+    assert g6.g6_open(-1) == g6.EINVAL
+    assert g6.g6_open(g6.MAX_HANDLES) == g6.EINVAL
+    z = np.zeros(3)
+    assert g6.g6_set_j_particle(0, 0, 0, 0.0, 0.0, 1.0, z, z, z, z, z) == g6.ESTATE
+    assert g6.g6calc_firsthalf(0, 0, 0, [], np.zeros((0, 3)), np.zeros((0, 3)), None, None, None, 0.0, None) == g6.ESTATE
+    acc = np.zeros((0, 3))
+    assert g6.g6calc_lasthalf(0, 0, 0, [], None, None, 0.0, None, acc, acc, np.zeros(0)) == g6.ESTATE
+    assert g6.g6_read_neighbour_list(0) == g6.ESTATE
+    assert g6.g6mi_set_precision(0, "ds") == g6.ESTATE
+    assert g6.g6_close(0) == g6.ESTATE
+    assert g6.g6_close(99) == g6.EINVAL
+
+
+def test_fortran_aliases_take_addresses(g6):
+    lib = ctypes.CDLL(g6.LIB_PATH)
+    f = lib.g6_npipes_
+    f.restype = ctypes.c_int
+    assert f() == g6.g6_npipes()
+    op = lib.g6_open_
+    op.restype = ctypes.c_int
+    op.argtypes = [ctypes.POINTER(ctypes.c_int)]
+    bad = ctypes.c_int(-5)
+    assert op(ctypes.byref(bad)) == g6.EINVAL

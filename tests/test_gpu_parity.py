@@ -1,0 +1,423 @@
+"""GPU parity: libg6mi (through its C ABI) against the float64 CPU oracle.
+
+Every GPU result is compared element by element with the oracle on the same
+seeded inputs.  The i-block handed to the GPU is the host-predicted state of
+the active particles (the client's job in the paper's CPU/GPU split); the
+j-memory is predicted independently on each side.
+"""
+
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def g6():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_0902_4463_amd as g6
+    return g6
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    return oracle
+
+
+@pytest.fixture()
+def sess(g6):
+    s = g6.Session(1)
+    yield s
+    s.close()
+
+
+def oracle_eval(orc, jm, slots, eps2, h2):
+    return orc.evaluate(jm, jm.meta.get("ti", 0.0), slots, eps2, h2, conditioning=True)
+
+
+def gpu_eval(sess, g6, jm, slots, ref, eps2, h2, prec, shape=(0, 0), neighbours=True):
+    g6.check(sess.id, g6.g6mi_set_precision(sess.id, prec))
+    g6.check(sess.id, g6.g6mi_set_shape(sess.id, *shape))
+    return sess.calc(jm.n, jm.meta.get("ti", 0.0), jm.index[slots], ref["xi"], ref["vi"], eps2, h2,
+                     neighbours=neighbours)
+
+
+def assert_parity(gpu, ref, jm, h2, prec, label, strict=True):
+    xp, _ = ref["_xp"], None
+    rep = parity.force_report(gpu, ref)
+    nn = parity.nn_report(gpu["nn_index"], ref["nn_index"], ref["nn_r2"], xp, jm.index, ref["xi"])
+    _say(f"[{label}] {prec}: acc_max={rep['acc_max']:.2e} jerk_max={rep['jerk_max']:.2e} "
+         f"pot_max={rep['pot_max']:.2e} cond={rep['acc_conditioned']}/{rep['jerk_conditioned']} "
+         f"nn_mismatch={nn['mismatch']} nn_ties={nn['ties']}")
+    if "nb_count" in gpu:
+        nb = parity.nb_report(gpu["nb_count"], gpu["nb_list"], ref["nb_count"], ref["nb_list"], xp, jm.index,
+                              ref["xi"], h2)
+        _say(f"[{label}] {prec}: nb_fail={nb['fail']} nb_ties={nb['ties']}")
+    else:
+        nb = dict(ok=True)
+    if strict:
+        assert rep["ok"], rep
+        assert nn["ok"], nn
+        assert nb["ok"], nb
+        # r2 of the nearest neighbour, where the index agrees
+        same = gpu["nn_index"] == ref["nn_index"]
+        fin = same & np.isfinite(ref["nn_r2"])
+        assert np.all(np.abs(gpu["nn_r2"][fin] - ref["nn_r2"][fin]) <= 1e-5 * ref["nn_r2"][fin])
+    return rep
+
+
+def with_xp(orc, jm, ref):
+    xp, _ = orc.predict(jm.meta.get("ti", 0.0), jm.t, jm.x, jm.v, jm.a2, jm.j6)
+    ref["_xp"] = xp
+    return ref
+
+
+# ------------------------------------------------------------------ C1
+
+@pytest.mark.parametrize("prec", ["ds", "fp64", "fp32"])
+def test_config_c1_full_evaluation(g6, orc, sess, prec):
+    """Equal-mass Plummer N=1024, eps = 1/64, all particles active."""
+    jm = workloads.config_c1()
+    slots = np.arange(jm.n)
+    eps2, h2 = jm.meta["eps2"], jm.meta["h2"]
+    ref = with_xp(orc, jm, oracle_eval(orc, jm, slots, eps2, h2))
+    sess.load(jm)
+    gpu = gpu_eval(sess, g6, jm, slots, ref, eps2, h2, prec)
+    rep = assert_parity(gpu, ref, jm, h2, prec, "C1", strict=prec != "fp32")
+    if prec == "fp32":
+        assert rep["acc_max"] < 1e-4 and rep["pot_max"] < 1e-5
+    if prec == "fp64":
+        assert rep["acc_max"] < 1e-12 and rep["jerk_max"] < 1e-11 and rep["pot_max"] < 1e-13
+    # Newton's third law on the GPU output, to the force tolerance
+    tot = (jm.m[:, None] * gpu["acc"]).sum(axis=0)
+    assert np.all(np.abs(tot) <= 2e-6 * np.sum(jm.m * np.linalg.norm(gpu["acc"], axis=1)))
+
+
+# --------------------------------------------- sizes spanning tiles and tails
+
+CASES = [(1, 1), (2, 1), (3, 3), (63, 7), (64, 64), (65, 7), (255, 64), (256, 256), (257, 257),
+         (4097, 300), (4097, 1), (5000, 7)]
+
+
+@pytest.mark.parametrize("n,ni", CASES)
+@pytest.mark.parametrize("prec", ["ds", "fp64"])
+def test_sizes_and_tails(g6, orc, sess, n, ni, prec):
+    jm = workloads.random_cluster(n, seed=1000 + n)
+    slots = workloads.active_set(n, ni, seed=n)
+    eps2, h2 = 1e-4, 0.05
+    ref = with_xp(orc, jm, oracle_eval(orc, jm, slots, eps2, h2))
+    sess.load(jm)
+    gpu = gpu_eval(sess, g6, jm, slots, ref, eps2, h2, prec)
+    assert_parity(gpu, ref, jm, h2, prec, f"N={n} ni={ni}")
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 37), (4, 3), (64, 7), (256, 1), (8, 100), (2, 13), (128, 2)])
+def test_launch_shapes(g6, orc, sess, shape):
+    """Every (i per workgroup, j-split) choice gives results within
+    tolerance, and the same shape twice gives identical bits."""
+    jm = workloads.random_cluster(3001, seed=77)
+    slots = workloads.active_set(3001, 300, seed=5)
+    eps2, h2 = 1e-3, 0.03
+    ref = with_xp(orc, jm, oracle_eval(orc, jm, slots, eps2, h2))
+    sess.load(jm)
+    a = gpu_eval(sess, g6, jm, slots, ref, eps2, h2, "ds", shape)
+    used = g6.g6mi_get_shape(sess.id)
+    assert used["i_per_group"] == shape[0] and used["j_splits"] == min(shape[1], (3001 + 255) // 256)
+    assert_parity(a, ref, jm, h2, "ds", f"shape={shape}")
+    b = gpu_eval(sess, g6, jm, slots, ref, eps2, h2, "ds", shape)
+    for key in ("acc", "jerk", "pot", "nn_index", "nn_r2", "nb_count", "nb_list"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_i_particles_outside_jmemory(g6, orc, sess):
+    """i-particles whose index is not stored in the j-memory feel every
+    j-particle (no self exclusion)."""
+    jm = workloads.random_cluster(700, seed=3)
+    rng = np.random.default_rng(4)
+    xi = rng.normal(size=(50, 3)) * 0.5
+    vi = rng.normal(size=(50, 3)) * 0.5
+    idx = np.arange(10 ** 6, 10 ** 6 + 50, dtype=np.int32)
+    xp, vp = orc.predict(jm.meta["ti"], jm.t, jm.x, jm.v, jm.a2, jm.j6)
+    ref = orc.force(xp, vp, jm.m, jm.index, xi, vi, idx, 1e-4, 0.05, conditioning=True)
+    ref["xi"], ref["vi"], ref["_xp"] = xi, vi, xp
+    sess.load(jm)
+    g6.g6mi_set_precision(sess.id, "ds")
+    g6.g6mi_set_shape(sess.id, 0, 0)
+    gpu = sess.calc(jm.n, jm.meta["ti"], idx, xi, vi, 1e-4, 0.05)
+    assert_parity(gpu, ref, jm, 0.05, "ds", "foreign i")
+
+
+# ------------------------------------------------------------- edge cases
+
+def test_neighbour_overflow(g6, orc, sess):
+    rng = np.random.default_rng(61)
+    n = 700
+    x = rng.normal(size=(n, 3)) * 0.01
+    jm = workloads.make_jmemory(x, rng.normal(size=(n, 3)), np.full(n, 1 / n), meta=dict(ti=0.0))
+    slots = np.arange(0, n, 50)
+    ref = oracle_eval(orc, jm, slots, 1e-6, 1.0)
+    sess.load(jm)
+    g6.g6mi_set_precision(sess.id, "ds")
+    g6.g6mi_set_shape(sess.id, 0, 0)
+    gpu = sess.calc(n, 0.0, jm.index[slots], ref["xi"], ref["vi"], 1e-6, 1.0)
+    assert gpu["nb_overflow"]
+    assert np.array_equal(gpu["nb_count"], ref["nb_count"])
+    for i in range(len(slots)):
+        row = gpu["nb_list"][i]
+        assert np.all(np.diff(row) > 0) and row.size == 256
+        assert not np.isin(jm.index[slots[i]], row)
+
+
+def test_nonfinite_output_is_flagged(g6, sess):
+    """eps = 0 with two distinct particles at the same place: the result is
+    not finite and lasthalf says so with return code 1."""
+    x = np.array([[0.0, 0, 0], [0.0, 0, 0], [1.0, 0, 0]])
+    jm = workloads.make_jmemory(x, np.zeros((3, 3)), np.ones(3), meta=dict(ti=0.0))
+    sess.load(jm)
+    g6.g6mi_set_precision(sess.id, "ds")
+    ni = 1
+    g6.g6_set_ti(sess.id, 0.0)
+    assert g6.g6calc_firsthalf(sess.id, 3, ni, [0], x[:1], np.zeros((1, 3)), None, None, None, 0.0, [0.1]) == 0
+    acc = np.zeros((1, 3)); jerk = np.zeros((1, 3)); pot = np.zeros(1)
+    assert g6.g6calc_lasthalf(sess.id, 3, ni, [0], x[:1], np.zeros((1, 3)), 0.0, [0.1], acc, jerk, pot) == g6.WARN
+
+
+def test_empty_j_and_empty_i(g6, sess):
+    jm = workloads.random_cluster(10, seed=9)
+    sess.load(jm)
+    g6.g6mi_set_precision(sess.id, "ds")
+    out = sess.calc(0, 0.0, np.array([3, 4], dtype=np.int32), jm.x[3:5], jm.v[3:5], 1e-4, 0.1)
+    assert np.all(out["acc"] == 0) and np.all(out["pot"] == 0) and np.all(out["jerk"] == 0)
+    assert np.all(out["nn_index"] == -1) and np.all(np.isinf(out["nn_r2"]))
+    assert np.all(out["nb_count"] == 0)
+    out = sess.calc(10, 0.0, np.zeros(0, dtype=np.int32), np.zeros((0, 3)), np.zeros((0, 3)), 1e-4, 0.1)
+    assert out["acc"].shape == (0, 3)
+
+
+def test_call_sequence_errors(g6, sess):
+    jm = workloads.random_cluster(20, seed=2)
+    sess.load(jm)
+    acc = np.zeros((2, 3)); jerk = np.zeros((2, 3)); pot = np.zeros(2)
+    idx = np.array([0, 1], dtype=np.int32)
+    assert g6.g6calc_lasthalf(sess.id, 20, 2, idx, None, None, 1e-4, None, acc, jerk, pot) == g6.ESTATE
+    assert g6.g6calc_firsthalf(sess.id, 21, 2, idx, jm.x[:2], jm.v[:2], None, None, None, 1e-4, None) == g6.EINVAL
+    assert g6.g6calc_lasthalf(sess.id, 21, 2, idx, None, None, 1e-4, None, acc, jerk, pot) == g6.EINVAL
+    assert g6.g6calc_firsthalf(sess.id, 20, 2, idx, jm.x[:2], jm.v[:2], None, None, None, 1e-4, None) == 0
+    assert g6.g6calc_lasthalf(sess.id, 20, 2, idx, None, None, 2e-4, None, acc, jerk, pot) == g6.EINVAL
+    assert g6.g6calc_firsthalf(sess.id, 20, 2, idx, jm.x[:2], jm.v[:2], None, None, None, -1.0, None) == g6.EINVAL
+    assert g6.g6calc_lasthalf(sess.id, 20, 2, idx, None, None, -1.0, None, acc, jerk, pot) == g6.EINVAL
+    bad = jm.x[:2].copy(); bad[0, 0] = np.nan
+    assert g6.g6calc_firsthalf(sess.id, 20, 2, idx, bad, jm.v[:2], None, None, None, 1e-4, None) == g6.EINVAL
+    assert g6.g6calc_lasthalf(sess.id, 20, 2, idx, None, None, 1e-4, None, acc, jerk, pot) == g6.EINVAL
+    assert g6.g6mi_set_shape(sess.id, 3, 1) == g6.EINVAL
+    assert g6.g6mi_set_precision(sess.id, 7) == g6.EINVAL
+
+
+def test_neighbour_lists_switch(g6, orc, sess):
+    """Turning neighbour lists off leaves forces bit-identical and reports
+    empty lists."""
+    jm = workloads.random_cluster(2000, seed=12)
+    slots = workloads.active_set(2000, 200, seed=1)
+    ref = with_xp(orc, jm, oracle_eval(orc, jm, slots, 1e-4, 0.05))
+    sess.load(jm)
+    on = gpu_eval(sess, g6, jm, slots, ref, 1e-4, 0.05, "ds")
+    g6.g6mi_set_neighbour_lists(sess.id, 0)
+    off = gpu_eval(sess, g6, jm, slots, ref, 1e-4, 0.05, "ds")
+    g6.g6mi_set_neighbour_lists(sess.id, 1)
+    for key in ("acc", "jerk", "pot", "nn_index"):
+        assert np.array_equal(on[key], off[key])
+    assert np.all(off["nb_count"] == 0)
+
+
+def test_set_j_particle_updates_between_calls(g6, orc, sess):
+    """Re-storing some j-particles (a corrector step) changes only what the
+    next calculation sees: results match the oracle on the updated memory."""
+    jm = workloads.random_cluster(1500, seed=14)
+    sess.load(jm)
+    rng = np.random.default_rng(2)
+    upd = rng.choice(1500, 100, replace=False)
+    jm.x[upd] += rng.normal(size=(100, 3)) * 0.01
+    jm.t[upd] = jm.meta["ti"]
+    zero = np.zeros(3)
+    for k in upd:
+        g6.check(sess.id, g6.g6_set_j_particle(sess.id, int(k), int(jm.index[k]), jm.t[k], 0.0, jm.m[k], zero,
+                                              jm.j6[k], jm.a2[k], jm.v[k], jm.x[k]))
+    slots = workloads.active_set(1500, 128, seed=3)
+    ref = with_xp(orc, jm, oracle_eval(orc, jm, slots, 1e-4, 0.05))
+    gpu = gpu_eval(sess, g6, jm, slots, ref, 1e-4, 0.05, "ds")
+    assert_parity(gpu, ref, jm, 0.05, "ds", "updated j")
+
+
+# ---------------------------------------------------- device-resident path
+
+def device_jmem(g6, sess, jm):
+    import torch
+    dev = torch.device("cuda")
+    d = dict(t=torch.tensor(jm.t, device=dev), m=torch.tensor(jm.m, device=dev),
+             index=torch.tensor(jm.index, device=dev), x=torch.tensor(jm.x, device=dev),
+             v=torch.tensor(jm.v, device=dev), a2=torch.tensor(jm.a2, device=dev),
+             j6=torch.tensor(jm.j6, device=dev))
+    g6.check(sess.id, g6.g6mi_set_j_particles_device(sess.id, jm.n, d["t"], d["m"], d["index"], d["x"], d["v"],
+                                                    d["a2"], d["j6"]))
+    torch.cuda.synchronize()
+    return d
+
+
+def device_calc(g6, sess, nj, islot, xi, vi, eps2, h2):
+    import torch
+    dev = torch.device("cuda")
+    ni = len(islot)
+    t_islot = torch.tensor(np.asarray(islot, dtype=np.int32), device=dev)
+    t_xi = torch.tensor(np.ascontiguousarray(xi), device=dev)
+    t_vi = torch.tensor(np.ascontiguousarray(vi), device=dev)
+    t_h2 = torch.tensor(np.broadcast_to(np.float64(h2), (ni,)).copy(), device=dev)
+    out = dict(acc=torch.empty((ni, 3), dtype=torch.float64, device=dev),
+               jerk=torch.empty((ni, 3), dtype=torch.float64, device=dev),
+               pot=torch.empty(ni, dtype=torch.float64, device=dev),
+               nnb=torch.empty(ni, dtype=torch.int32, device=dev),
+               r2nn=torch.empty(ni, dtype=torch.float64, device=dev))
+    stream = torch.cuda.current_stream()
+    g6.check(sess.id, g6.g6mi_calc_device(sess.id, nj, ni, t_islot, t_xi, t_vi, eps2, t_h2, out["acc"],
+                                          out["jerk"], out["pot"], out["nnb"], out["r2nn"], stream=stream))
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def test_device_path_matches_host_path(g6, orc, sess):
+    jm = workloads.random_cluster(3000, seed=17)
+    slots = workloads.active_set(3000, 333, seed=2)
+    ref = with_xp(orc, jm, oracle_eval(orc, jm, slots, 1e-4, 0.05))
+    sess.load(jm)
+    host = gpu_eval(sess, g6, jm, slots, ref, 1e-4, 0.05, "ds")
+    device_jmem(g6, sess, jm)
+    g6.g6_set_ti(sess.id, jm.meta["ti"])
+    dv = device_calc(g6, sess, jm.n, slots, ref["xi"], ref["vi"], 1e-4, 0.05)
+    for k_host, k_dev in (("acc", "acc"), ("jerk", "jerk"), ("pot", "pot"), ("nn_index", "nnb"), ("nn_r2", "r2nn")):
+        assert np.array_equal(host[k_host], dv[k_dev]), k_host
+
+
+# --------------------------------------- full-size workloads, sampled outputs
+
+@functools.lru_cache(maxsize=1)
+def c3_case(n=2 ** 20):
+    return workloads.config_c3(n=n)
+
+
+@pytest.mark.parametrize("prec", ["ds", "fp64"])
+def test_config_c3_full_size_sampled(g6, orc, sess, prec):
+    """Plummer N=2^20 with Salpeter masses: all 2^20 particles active (the
+    benchmark's launch), 512 sampled i-particles checked against the
+    oracle.  The i-block is the stored (unpredicted) state, as in the
+    benchmark; both sides get the same arrays."""
+    import torch
+    jm = c3_case()
+    n = jm.n
+    eps2, h2, ti = jm.meta["eps2"], jm.meta["h2"], jm.meta["ti"]
+    _say(f"[C3] loading N={n} ({prec})")
+    device_jmem(g6, sess, jm)
+    g6.g6mi_set_precision(sess.id, prec)
+    g6.g6mi_set_shape(sess.id, 0, 0)
+    g6.g6_set_ti(sess.id, ti)
+    slots = np.arange(n, dtype=np.int32)
+    _say(f"[C3] running ni={n} ({prec})")
+    dv = device_calc(g6, sess, n, slots, jm.x, jm.v, eps2, h2)
+    sample = workloads.active_set(n, 512, seed=33)
+    xp, vp = orc.predict(ti, jm.t, jm.x, jm.v, jm.a2, jm.j6)
+    ref = orc.force(xp, vp, jm.m, jm.index, jm.x[sample], jm.v[sample], jm.index[sample], eps2, h2,
+                    conditioning=True)
+    gpu = dict(acc=dv["acc"][sample], jerk=dv["jerk"][sample], pot=dv["pot"][sample])
+    rep = parity.force_report(gpu, ref)
+    nn = parity.nn_report(dv["nnb"][sample], ref["nn_index"], ref["nn_r2"], xp, jm.index, jm.x[sample])
+    _say(f"[C3] {prec}: {rep} nn={nn}")
+    assert rep["ok"], rep
+    assert nn["ok"], nn
+    # neighbour lists of the sampled particles
+    assert g6.g6_read_neighbour_list(sess.id) in (0, 1)
+    cnt = np.zeros(len(sample), dtype=np.int64)
+    lists = np.full((len(sample), 256), -1, dtype=np.int32)
+    ln = np.zeros(1, dtype=np.int32)
+    for q, i in enumerate(sample):
+        buf = np.zeros(256, dtype=np.int32)
+        g6.g6_get_neighbour_list(sess.id, int(i), 256, ln, buf)
+        cnt[q] = ln[0]
+        lists[q, :min(256, ln[0])] = buf[:min(256, ln[0])]
+    nb = parity.nb_report(cnt, lists, ref["nb_count"], ref["nb_list"], xp, jm.index, jm.x[sample], h2)
+    _say(f"[C3] {prec}: nb={nb}")
+    assert nb["ok"], nb
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("k", [0, 3, 7, 12, 16])
+def test_config_c3_active_blocks(g6, orc, sess, k):
+    """Active blocks of 2^k particles against all 2^20 (the throughput
+    sweep), DS, up to 256 sampled i-particles checked."""
+    jm = c3_case()
+    n = jm.n
+    eps2, h2, ti = jm.meta["eps2"], jm.meta["h2"], jm.meta["ti"]
+    device_jmem(g6, sess, jm)
+    g6.g6mi_set_precision(sess.id, "ds")
+    g6.g6mi_set_shape(sess.id, 0, 0)
+    g6.g6_set_ti(sess.id, ti)
+    slots = workloads.active_set(n, 2 ** k, seed=3)
+    _say(f"[C3 k={k}] running")
+    dv = device_calc(g6, sess, n, slots, jm.x[slots], jm.v[slots], eps2, h2)
+    pick = np.arange(len(slots)) if len(slots) <= 256 else workloads.active_set(len(slots), 256, seed=k)
+    xp, vp = orc.predict(ti, jm.t, jm.x, jm.v, jm.a2, jm.j6)
+    s = slots[pick]
+    ref = orc.force(xp, vp, jm.m, jm.index, jm.x[s], jm.v[s], jm.index[s], eps2, h2, conditioning=True)
+    gpu = dict(acc=dv["acc"][pick], jerk=dv["jerk"][pick], pot=dv["pot"][pick])
+    rep = parity.force_report(gpu, ref)
+    nn = parity.nn_report(dv["nnb"][pick], ref["nn_index"], ref["nn_r2"], xp, jm.index, jm.x[s])
+    _say(f"[C3 k={k}] {rep} nn={nn}")
+    assert rep["ok"] and nn["ok"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "ds", "fp32"])
+def test_config_c5_precision_stress(g6, orc, sess, prec):
+    """Plummer N=2^18 with 5% hard-binary members, translated by 1e4,
+    eps = 0.  FP64 must meet the tolerances; DS and FP32 errors are
+    reported (the 2^-48 DS resolution at |x| = 1e4 is ~4e-11, comparable to
+    the tightest binaries' separations)."""
+    jm = workloads.config_c5()
+    n = jm.n
+    eps2, h2 = jm.meta["eps2"], jm.meta["h2"]
+    device_jmem(g6, sess, jm)
+    g6.g6mi_set_precision(sess.id, prec)
+    g6.g6mi_set_shape(sess.id, 0, 0)
+    g6.g6_set_ti(sess.id, 0.0)
+    nb_ = jm.meta["n_binaries"]
+    sample = np.concatenate([np.arange(0, 2 * nb_, 2 * nb_ // 128), workloads.active_set(n - 2 * nb_, 128, 5) + 2 * nb_])
+    sample = np.unique(sample).astype(np.int32)
+    _say(f"[C5] running {prec}")
+    dv = device_calc(g6, sess, n, sample, jm.x[sample], jm.v[sample], eps2, h2)
+    ref = orc.force(jm.x, jm.v, jm.m, jm.index, jm.x[sample], jm.v[sample], jm.index[sample], eps2, h2,
+                    conditioning=True)
+    gpu = dict(acc=dv["acc"], jerk=dv["jerk"], pot=dv["pot"])
+    finite = np.isfinite(gpu["acc"]).all(axis=1) & np.isfinite(gpu["jerk"]).all(axis=1)
+    rep = parity.force_report({k: np.where(np.isfinite(v), v, 0) for k, v in gpu.items()}, ref)
+    is_bin = jm.meta["is_binary"][sample]
+    ea, ej, ep = parity.rel_errors({k: np.where(np.isfinite(v), v, 0) for k, v in gpu.items()}, ref)
+    _say(f"[C5] {prec}: nonfinite={int((~finite).sum())} acc_max(bin)={ea[is_bin].max():.2e} "
+         f"acc_max(single)={ea[~is_bin].max():.2e} jerk_max={ej.max():.2e} pot_max={ep.max():.2e}")
+    if prec == "fp64":
+        assert finite.all() and rep["ok"], rep
+        nn = parity.nn_report(dv["nnb"], ref["nn_index"], ref["nn_r2"], jm.x, jm.index, jm.x[sample])
+        assert nn["ok"], nn
+    if prec == "ds":
+        assert finite.all()
+        # single stars are far from any partner: DS meets the tolerance there
+        assert ea[~is_bin].max() <= parity.TOL_ACC

@@ -354,3 +354,15 @@ def test_tiny_systems_against_50_digit_arithmetic(oracle_mod):
             assert np.all(np.abs(res["acc"][i] - np.array([float(c) for c in A])) <= 1e-13 * an)
             assert np.all(np.abs(res["jerk"][i] - np.array([float(c) for c in J])) <= 1e-12 * jn)
             assert abs(res["pot"][i] - float(P)) <= 1e-14 * abs(float(P))
+
+
+def test_conditioning_sums(oracle_mod):
+    """The magnitude sums bound the vector sums (triangle inequality) and
+    equal them for a single pair."""
+    jm = workloads.random_cluster(300, seed=81)
+    res = oracle_mod.force(jm.x, jm.v, jm.m, jm.index, jm.x, jm.v, jm.index, 1e-3, conditioning=True)
+    assert np.all(res["acc_abs"] >= np.linalg.norm(res["acc"], axis=1) * (1 - 1e-14))
+    assert np.all(res["jerk_abs"] >= np.linalg.norm(res["jerk"], axis=1) * (1 - 1e-14))
+    two = oracle_mod.force(jm.x[:2], jm.v[:2], jm.m[:2], [0, 1], jm.x[:1], jm.v[:1], [0], 1e-3, conditioning=True)
+    assert two["acc_abs"][0] == pytest.approx(np.linalg.norm(two["acc"][0]), rel=1e-14)
+    assert two["jerk_abs"][0] == pytest.approx(np.linalg.norm(two["jerk"][0]), rel=1e-14)
