@@ -33,6 +33,32 @@ FLOP_PER_PAIR = 60          # Sec. 3.1 convention, used for every variant
 PEAK_FP32_TFLOPS = 157.3    # MI355X vector FP32 (dense)
 PEAK_FP64_TFLOPS = 78.6     # MI355X vector FP64
 METRIC = "pair interactions/s & Gflop/s (60 flop/pair) at N=2^20, DS vs FP64 at stated err"
+KERNEL_SOURCES = ("paper_0902_4463_amd/csrc/g6mi_kernels.hip", "paper_0902_4463_amd/csrc/g6mi_internal.h",
+                  "paper_0902_4463_amd/csrc/g6mi_api.cpp")
+TRAFFIC_PROFILE = "profiles/force_wide_ds_plummer_N1048576_traffic.md"
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()
+
+
+def profiled_traffic():
+    """HBM bytes per launch of the DS interaction kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the kernel sources
+    changed since the counters were taken."""
+    try:
+        text = open(os.path.join(ROOT, TRAFFIC_PROFILE)).read()
+    except OSError:
+        return None
+    vals = dict(line.split(": ", 1) for line in text.splitlines()
+                if line.startswith(("traffic_bytes_per_launch:", "kernel_source_sha256:")))
+    if vals.get("kernel_source_sha256", "").strip() != kernel_source_hash():
+        return None
+    return float(vals["traffic_bytes_per_launch:".rstrip(":")])
 
 
 def log(*a):
@@ -95,13 +121,19 @@ def main():
                pot=torch.empty(ni, dtype=torch.float64, device=dev),
                nnb=torch.empty(ni, dtype=torch.int32, device=dev),
                r2nn=torch.empty(ni, dtype=torch.float64, device=dev))
-    stream = torch.cuda.current_stream()
+    # a stream of our own (default priority): the library launches on it and
+    # the HIP events below are recorded on it
+    stream = torch.cuda.Stream()
 
     def step():
         g6.check(hid, g6.g6mi_calc_device(hid, n, ni, islot, xi, vi, eps2, th2, out["acc"], out["jerk"],
                                           out["pot"], out["nnb"], out["r2nn"], stream=stream))
 
     def run(variant, steps, warmup):
+        with torch.cuda.stream(stream):
+            return _run(variant, steps, warmup)
+
+    def _run(variant, steps, warmup):
         g6.check(hid, g6.g6mi_set_precision(hid, variant))
         for w in range(warmup):
             step()
@@ -135,9 +167,14 @@ def main():
     value = pairs / (main_run["ms_per_step"] * 1e-3)
     force_tflops = FLOP_PER_PAIR * pairs / (main_run["force_ms"] * 1e-3) / 1e12
     peak = PEAK_FP64_TFLOPS if args.variant == "fp64" else PEAK_FP32_TFLOPS
+    default_run = (args.variant == "ds" and n == 2 ** 20 and ni == n and not args.shape
+                   and not args.no_neighbour_lists)
+    traffic = profiled_traffic() if default_run else None
     roofline = dict(bound="alu", achieved=round(force_tflops, 3), peak=peak, unit="TFLOP/s",
-                    frac=round(force_tflops / peak, 4), traffic=None,
-                    kernel=f"force_kernel<{args.variant}>", flop_per_pair=FLOP_PER_PAIR,
+                    frac=round(force_tflops / peak, 4), traffic=traffic,
+                    traffic_source=TRAFFIC_PROFILE if traffic else None,
+                    kernel=("force_wide" if main_run["shape"]["i_per_group"] == 512 else "force_kernel")
+                    + f"<{args.variant}>", flop_per_pair=FLOP_PER_PAIR,
                     pairs_per_launch=pairs, avg_launch_ms=round(main_run["force_ms"], 4))
 
     variants = {}

@@ -195,8 +195,10 @@ int g6mi_get_precision(int id);
 int g6mi_set_neighbour_lists(int id, int on);
 
 /* Override the launch shape of the interaction kernel: i-particles per
- * workgroup (a power of two, 1..256) and number of j-splits (1..4096).
- * 0 restores the automatic choice.  Returns 0 or G6MI_EINVAL. */
+ * workgroup (a power of two, 1..512; 512 means two i-particles per lane,
+ * 256 or fewer one per lane or several lanes per i-particle) and number of
+ * j-splits (1..4096).  0 restores the automatic choice.  Returns 0 or
+ * G6MI_EINVAL. */
 int g6mi_set_shape(int id, int i_per_group, int j_splits);
 
 /* Launch shape used by the last calculation: i per workgroup, j-splits,

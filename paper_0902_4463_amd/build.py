@@ -33,13 +33,15 @@ def flags(extra=()):
             "-I", os.path.join(ROOT, "include"), "-Wall", *extra]
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    cmd = [hipcc(), *flags(extra), "-shared", "-o", LIB + ".tmp", *SOURCES]
+def build(verbose: bool = False, extra=(), out: str = LIB) -> str:
+    """Compile the library to ``out``; ``extra`` adds compiler options such
+    as -DG6MI_TILE=512 (the tuning knobs in csrc/g6mi_internal.h)."""
+    cmd = [hipcc(), *flags(extra), "-shared", "-o", out + ".tmp", *SOURCES]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

@@ -262,25 +262,38 @@ int ilog2(int v) {
   return l;
 }
 
-// Launch shape.  i-particles per workgroup: the smallest power of two
-// covering the block, at most 256 (one i per lane); below 256 the spare
-// lanes split the j-tile among themselves (Sec. 2.3, Fig. accMP1).
-// j-splits: enough workgroups for ~4 per compute unit (Sec. 2.3, Fig. accGPU
-// splits j over all multiprocessors), never more than there are tiles.
+// Launch shape.  i-particles per workgroup: 512 (two per lane) for blocks
+// of at least 512, else the smallest power of two covering the block, at
+// most 256 (one per lane); below 256 the spare lanes split the j-tile among
+// themselves (Sec. 2.3, Fig. accMP1).
+// j-splits: enough workgroups for G6MI_WG_PER_CU per compute unit (Sec. 2.3,
+// Fig. accGPU splits j over all multiprocessors), each split at least
+// kMinTiles tiles long.  Many short workgroups keep the last round on each
+// CU small (measured: 8 splits of 2^20 j beat 1 split by 7%).
+#ifndef G6MI_WG_PER_CU
+#define G6MI_WG_PER_CU 64
+#endif
+constexpr int kWaveTarget = G6MI_WG_PER_CU;
+constexpr int kMinTiles = 8;
+
 void choose_shape(Handle &h, int ni, int nj, int &ipw, int &nsplit) {
   const int ntiles = (nj + kTile - 1) / kTile;
   if (h.user_ipw) ipw = h.user_ipw;
+  else if (ni >= 2 * kWG) ipw = 2 * kWG; // two i-particles per lane
   else {
     ipw = kWG;
     while (ipw > 1 && ipw / 2 >= ni) ipw /= 2;
   }
   const long nib = (ni + ipw - 1) / ipw;
-  if (h.user_nsplit) nsplit = h.user_nsplit;
-  else {
-    const long target = 4L * std::max(1, h.ncu);
+  if (h.user_nsplit) {
+    nsplit = std::max(1, std::min(h.user_nsplit, std::max(1, ntiles)));
+  } else {
+    // enough workgroups that the last round on each compute unit is a small
+    // fraction of the work, each split at least kMinTiles tiles long
+    const long target = static_cast<long>(kWaveTarget) * std::max(1, h.ncu);
     nsplit = static_cast<int>(std::max(1L, (target + nib - 1) / std::max(1L, nib)));
+    nsplit = std::max(1, std::min(nsplit, std::max(1, ntiles / kMinTiles)));
   }
-  nsplit = std::max(1, std::min(nsplit, std::max(1, ntiles)));
   nsplit = std::min(nsplit, 4096);
 }
 
@@ -698,7 +711,7 @@ G6MI_API int g6mi_set_neighbour_lists(int id, int on) {
 G6MI_API int g6mi_set_shape(int id, int i_per_group, int j_splits) {
   Handle *h = get_open(id);
   if (!h) return code_for_missing(id);
-  if (i_per_group < 0 || i_per_group > kWG || (i_per_group & (i_per_group - 1)) ||
+  if (i_per_group < 0 || i_per_group > 2 * kWG || (i_per_group & (i_per_group - 1)) ||
       j_splits < 0 || j_splits > 4096)
     return fail(h, G6MI_EINVAL, "bad launch shape");
   h->user_ipw = i_per_group;

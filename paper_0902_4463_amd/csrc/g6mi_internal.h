@@ -9,9 +9,23 @@
 
 namespace g6mi {
 
-constexpr int kWG = 256;    // lanes per workgroup: four wave64
-constexpr int kTile = 256;  // j-records staged in LDS per tile
-constexpr int kNbMax = 256; // neighbour slots per i-particle
+// Build-time tuning knobs (defaults chosen by measurement on MI355X).
+#ifndef G6MI_TILE
+#define G6MI_TILE 256 // j-records staged in LDS per tile
+#endif
+#ifndef G6MI_GROUP
+#define G6MI_GROUP 8 // j-records per nearest-neighbour group
+#endif
+#ifndef G6MI_GROUP_UNROLL
+#define G6MI_GROUP_UNROLL 2 // groups per unrolled loop body
+#endif
+#ifndef G6MI_WIDE_WAVES
+#define G6MI_WIDE_WAVES 4 // register budget of the wide kernel: waves per SIMD (0: free)
+#endif
+
+constexpr int kWG = 256;          // lanes per workgroup: four wave64
+constexpr int kTile = G6MI_TILE;  // j-records staged in LDS per tile
+constexpr int kNbMax = 256;       // neighbour slots per i-particle
 
 // Predicted j-record sizes in bytes, one record per j-slot:
 //   DS   : float4{x_hi, m}, float4{x_lo, 0}, float4{v, 0}  = 48 B

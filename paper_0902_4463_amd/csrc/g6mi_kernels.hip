@@ -347,6 +347,292 @@ __global__ __launch_bounds__(kWG) void force_kernel(ForceArgs a) {
   }
 }
 
+// ------------------------------------------------- interaction, wide blocks
+
+// Separation of i and one j-record: r = x_j - x_i (Eq. (3) for DS), the
+// velocity difference and r^2 without softening.
+template <int PREC>
+__device__ __forceinline__ void separation(const IState<PREC> &st, const float4 *__restrict__ rec,
+                                           real_t<PREC> d[3], real_t<PREC> w[3], real_t<PREC> &mj) {
+  if constexpr (PREC == G6MI_PREC_DS) {
+    const float4 p = rec[0], q = rec[1], v = rec[2];
+    d[0] = (p.x - st.xh[0]) + (q.x - st.xl[0]);
+    d[1] = (p.y - st.xh[1]) + (q.y - st.xl[1]);
+    d[2] = (p.z - st.xh[2]) + (q.z - st.xl[2]);
+    w[0] = v.x - st.v[0];
+    w[1] = v.y - st.v[1];
+    w[2] = v.z - st.v[2];
+    mj = p.w;
+  } else if constexpr (PREC == G6MI_PREC_FP32) {
+    const float4 p = rec[0], v = rec[1];
+    d[0] = p.x - st.x[0];
+    d[1] = p.y - st.x[1];
+    d[2] = p.z - st.x[2];
+    w[0] = v.x - st.v[0];
+    w[1] = v.y - st.v[1];
+    w[2] = v.z - st.v[2];
+    mj = p.w;
+  } else {
+    const double2 *r2 = reinterpret_cast<const double2 *>(rec);
+    const double2 p0 = r2[0], p1 = r2[1], w0 = r2[2], w1 = r2[3];
+    d[0] = p0.x - st.x[0];
+    d[1] = p0.y - st.x[1];
+    d[2] = p1.x - st.x[2];
+    w[0] = w0.x - st.v[0];
+    w[1] = w0.y - st.v[1];
+    w[2] = w1.x - st.v[2];
+    mj = p1.y;
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ real_t<PREC> r2_of(const IState<PREC> &st, const float4 *__restrict__ rec) {
+  real_t<PREC> d[3], w[3], mj;
+  separation<PREC>(st, rec, d, w, mj);
+  return d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+}
+
+// The pair terms of Sec. 2.3 added to the tile sums; returns r^2 (without
+// softening) for the neighbour search.  No self test: the caller only uses
+// it on tiles that hold neither i-particle's own slot.
+template <int PREC>
+__device__ __forceinline__ real_t<PREC> pair_core(IState<PREC> &st, const float4 *__restrict__ rec,
+                                                  real_t<PREC> eps2) {
+  using R = real_t<PREC>;
+  R d[3], w[3], mj;
+  separation<PREC>(st, rec, d, w, mj);
+  const R r2u = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  const R s = r2u + eps2;
+  R rinv;
+  if constexpr (PREC == G6MI_PREC_FP64) rinv = rsqrt_f64(s);
+  else rinv = __builtin_amdgcn_rsqf(s);
+  const R rinv2 = rinv * rinv;
+  const R mr = mj * rinv;
+  const R mr3 = mr * rinv2;
+  const R rv = d[0] * w[0] + d[1] * w[1] + d[2] * w[2];
+  const R mr3t = mr3 * (rv * rinv2);
+  st.tp += mr;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    st.ta[k] += mr3 * d[k];
+    st.tj1[k] += mr3 * w[k];
+    st.tj2[k] += mr3t * d[k];
+  }
+  return r2u;
+}
+
+template <int PREC>
+__device__ __forceinline__ void load_i(IState<PREC> &st, const ForceArgs &a, int i, bool valid,
+                                       int &islot, real_t<PREC> &h2) {
+  using R = real_t<PREC>;
+  double xi[3] = {0.0, 0.0, 0.0}, vi[3] = {0.0, 0.0, 0.0};
+  islot = -1;
+  h2 = R(-INFINITY);
+  if (valid) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      xi[d] = a.xi[3 * static_cast<size_t>(i) + d];
+      vi[d] = a.vi[3 * static_cast<size_t>(i) + d];
+    }
+    islot = a.islot[i];
+    h2 = static_cast<R>(a.h2[i]);
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if constexpr (PREC == G6MI_PREC_DS) {
+      st.xh[d] = static_cast<float>(xi[d]);
+      st.xl[d] = static_cast<float>(xi[d] - static_cast<double>(st.xh[d]));
+      st.v[d] = static_cast<float>(vi[d]);
+    } else {
+      st.x[d] = static_cast<R>(xi[d]);
+      st.v[d] = static_cast<R>(vi[d]);
+    }
+    st.ta[d] = st.tj1[d] = st.tj2[d] = R(0);
+  }
+  st.tp = R(0);
+}
+
+// Float64 running totals of one i-particle: the tile sums are folded in
+// after every tile (float32 variants sum at most kTile terms in float32).
+struct Totals {
+  double acc[3], jrk[3], pot;
+};
+
+template <int PREC>
+__device__ __forceinline__ void fold(IState<PREC> &st, Totals &t) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    t.acc[d] += static_cast<double>(st.ta[d]);
+    t.jrk[d] += static_cast<double>(st.tj1[d]) - 3.0 * static_cast<double>(st.tj2[d]);
+    st.ta[d] = st.tj1[d] = st.tj2[d] = real_t<PREC>(0);
+  }
+  t.pot += static_cast<double>(st.tp);
+  st.tp = real_t<PREC>(0);
+}
+
+__device__ __forceinline__ void nb_append(int *__restrict__ nb_count, int *__restrict__ nb_slot,
+                                          int i, int jslot) {
+  const int pos = atomicAdd(nb_count + i, 1);
+  if (pos < kNbMax) nb_slot[static_cast<size_t>(i) * kNbMax + pos] = jslot;
+}
+
+// Wide blocks: each lane owns two i-particles (i0 = base + tid and
+// i1 = base + 256 + tid, 512 per workgroup) and every lane of a wave reads
+// the same j-record from LDS (a broadcast), so one LDS record serves 128
+// pairs.  Grid: x = i-blocks of 512, y = j-splits.
+//
+// The j-loop runs in groups of kGroup records.  Nearest neighbour: one
+// min() per pair; once per group the group minimum is compared with the
+// running best and the group's first slot remembered; the exact slot is
+// recovered at the end by re-examining that one group (first minimum wins,
+// as in a sequential scan).  Neighbour lists need no per-pair test: a group
+// holds a neighbour of i exactly when its minimum r^2 is below h_i^2, and
+// only such groups are re-examined.
+// Tiles that contain an i-particle's own slot, and the ragged last tile,
+// take the per-pair path with explicit self exclusion.
+constexpr int kGroup = G6MI_GROUP;
+static_assert(kTile / kGroup <= 32, "one mask bit per group");
+static_assert(kTile % kGroup == 0, "whole groups per tile");
+
+#if G6MI_WIDE_WAVES > 0
+#define G6MI_WIDE_BOUNDS __launch_bounds__(kWG, G6MI_WIDE_WAVES)
+#else
+#define G6MI_WIDE_BOUNDS __launch_bounds__(kWG)
+#endif
+
+template <int PREC, bool NBL>
+__global__ G6MI_WIDE_BOUNDS void force_wide(ForceArgs a) {
+  using R = real_t<PREC>;
+  constexpr int REC = rec4<PREC>();
+  constexpr int kLoads = kTile * REC / kWG; // 16-byte loads per lane per tile
+  static_assert(kTile * REC % kWG == 0, "whole loads per lane");
+  __shared__ __attribute__((aligned(16))) float4 tile[kTile * REC];
+
+  const int tid = threadIdx.x;
+  const int i0 = blockIdx.x * (2 * kWG) + tid;
+  const int i1 = i0 + kWG;
+  const bool v0 = i0 < a.ni, v1 = i1 < a.ni;
+  IState<PREC> s0, s1;
+  int slot0, slot1;
+  R h20, h21;
+  load_i<PREC>(s0, a, i0, v0, slot0, h20);
+  load_i<PREC>(s1, a, i1, v1, slot1, h21);
+  const R eps2 = static_cast<R>(a.eps2);
+  Totals t0 = {{0, 0, 0}, {0, 0, 0}, 0}, t1 = {{0, 0, 0}, {0, 0, 0}, 0};
+  // nearest neighbour: fast-path best r^2 and its group; exact path best
+  R gbest0 = R(INFINITY), gbest1 = R(INFINITY);
+  int grp0 = -1, grp1 = -1;
+  R ebest0 = R(INFINITY), ebest1 = R(INFINITY);
+  int eslot0 = -1, eslot1 = -1;
+
+  const int ntiles = (a.nj + kTile - 1) / kTile;
+  const int per = (ntiles + gridDim.y - 1) / gridDim.y;
+  const int tb = blockIdx.y * per;
+  const int te = min(ntiles, tb + per);
+  const float4 *jp = static_cast<const float4 *>(a.jpred);
+
+  for (int tt = tb; tt < te; ++tt) {
+    const int jbase = tt * kTile;
+    const int cnt = min(kTile, a.nj - jbase);
+    __syncthreads();
+    {
+      // coalesced 16-byte loads of the tile into LDS (records < nj only)
+      const float4 *src = jp + static_cast<size_t>(jbase) * REC;
+      const int n4 = cnt * REC;
+#pragma unroll
+      for (int q = 0; q < kLoads; ++q) {
+        const int idx = q * kWG + tid;
+        if (idx < n4) tile[idx] = src[idx];
+      }
+    }
+    __syncthreads();
+    const bool self_here = (slot0 >= jbase && slot0 < jbase + cnt) || (slot1 >= jbase && slot1 < jbase + cnt);
+    if (cnt < kTile || __any(self_here)) {
+      for (int jj = 0; jj < cnt; ++jj) {
+        pair<PREC, true, NBL>(s0, tile + jj * REC, jbase + jj, slot0, eps2, h20, ebest0, eslot0,
+                              a.nb_count + (v0 ? i0 : 0),
+                              a.nb_slot + static_cast<size_t>(v0 ? i0 : 0) * kNbMax);
+        pair<PREC, true, NBL>(s1, tile + jj * REC, jbase + jj, slot1, eps2, h21, ebest1, eslot1,
+                              a.nb_count + (v1 ? i1 : 0),
+                              a.nb_slot + static_cast<size_t>(v1 ? i1 : 0) * kNbMax);
+      }
+    } else {
+      // bit k of nbm0 / nbm1: group k holds a neighbour of i0 / i1
+      unsigned nbm0 = 0u, nbm1 = 0u;
+#pragma unroll G6MI_GROUP_UNROLL
+      for (int g = 0; g < kTile; g += kGroup) {
+        R m0 = R(INFINITY), m1 = R(INFINITY);
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+          const float4 *rec = tile + (g + u) * REC;
+          m0 = fmin(m0, pair_core<PREC>(s0, rec, eps2));
+          m1 = fmin(m1, pair_core<PREC>(s1, rec, eps2));
+        }
+        if (m0 < gbest0) {
+          gbest0 = m0;
+          grp0 = jbase + g;
+        }
+        if (m1 < gbest1) {
+          gbest1 = m1;
+          grp1 = jbase + g;
+        }
+        if constexpr (NBL) {
+          // the group minimum also tells whether any record is a neighbour
+          nbm0 |= (m0 < h20 ? 1u : 0u) << (g / kGroup);
+          nbm1 |= (m1 < h21 ? 1u : 0u) << (g / kGroup);
+        }
+      }
+      if constexpr (NBL) {
+        // rare: append the neighbours of the flagged groups
+        while (nbm0 | nbm1) {
+          const int k = __builtin_ctz(nbm0 | nbm1);
+          const unsigned bit = 1u << k;
+          for (int u = 0; u < kGroup; ++u) {
+            const int jj = k * kGroup + u;
+            const float4 *rec = tile + jj * REC;
+            if ((nbm0 & bit) && r2_of<PREC>(s0, rec) < h20) nb_append(a.nb_count, a.nb_slot, i0, jbase + jj);
+            if ((nbm1 & bit) && r2_of<PREC>(s1, rec) < h21) nb_append(a.nb_count, a.nb_slot, i1, jbase + jj);
+          }
+          nbm0 &= ~bit;
+          nbm1 &= ~bit;
+        }
+      }
+    }
+    fold<PREC>(s0, t0);
+    fold<PREC>(s1, t1);
+  }
+
+  // exact slot of the fast-path nearest neighbour: re-examine its group
+  // (records are read from global memory; every slot is < nj)
+  auto resolve = [&](const IState<PREC> &st, int grp, R &best, int &bslot) {
+    if (grp < 0) return;
+    for (int u = 0; u < kGroup; ++u) {
+      const R r = r2_of<PREC>(st, jp + static_cast<size_t>(grp + u) * REC);
+      if (r < best || (r == best && grp + u < bslot)) {
+        best = r;
+        bslot = grp + u;
+      }
+    }
+  };
+  resolve(s0, grp0, ebest0, eslot0);
+  resolve(s1, grp1, ebest1, eslot1);
+
+  const size_t ni = static_cast<size_t>(a.ni);
+  auto store = [&](int i, const Totals &t, R best, int bslot) {
+    double *p = a.part + static_cast<size_t>(blockIdx.y) * 7 * ni + i;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      p[d * ni] = t.acc[d];
+      p[(3 + d) * ni] = t.jrk[d];
+    }
+    p[6 * ni] = t.pot;
+    a.nn_r2[blockIdx.y * ni + i] = static_cast<double>(best);
+    a.nn_slot[blockIdx.y * ni + i] = bslot;
+  };
+  if (v0) store(i0, t0, ebest0, eslot0);
+  if (v1) store(i1, t1, ebest1, eslot1);
+}
+
 // --------------------------------------------------------------- reduction
 
 // One thread per i-particle: float64 sum over the j-splits in split order,
@@ -477,7 +763,12 @@ hipError_t launch_predict(int prec, int nj, double ti, const JMem &jm, void *out
 
 template <int PREC>
 static void launch_force_prec(bool nbl, const ForceArgs &a, dim3 grid, hipStream_t s) {
-  if (nbl)
+  if (a.ipw == 2 * kWG) {
+    if (nbl)
+      hipLaunchKernelGGL((force_wide<PREC, true>), grid, dim3(kWG), 0, s, a);
+    else
+      hipLaunchKernelGGL((force_wide<PREC, false>), grid, dim3(kWG), 0, s, a);
+  } else if (nbl)
     hipLaunchKernelGGL((force_kernel<PREC, true>), grid, dim3(kWG), 0, s, a);
   else
     hipLaunchKernelGGL((force_kernel<PREC, false>), grid, dim3(kWG), 0, s, a);

@@ -125,12 +125,13 @@ def test_sizes_and_tails(g6, orc, sess, n, ni, prec):
     assert_parity(gpu, ref, jm, h2, prec, f"N={n} ni={ni}")
 
 
-@pytest.mark.parametrize("shape", [(1, 1), (1, 37), (4, 3), (64, 7), (256, 1), (8, 100), (2, 13), (128, 2)])
+@pytest.mark.parametrize("shape", [(1, 1), (1, 37), (4, 3), (64, 7), (256, 1), (8, 100), (2, 13), (128, 2),
+                                   (512, 1), (512, 5)])
 def test_launch_shapes(g6, orc, sess, shape):
     """Every (i per workgroup, j-split) choice gives results within
     tolerance, and the same shape twice gives identical bits."""
     jm = workloads.random_cluster(3001, seed=77)
-    slots = workloads.active_set(3001, 300, seed=5)
+    slots = workloads.active_set(3001, 700, seed=5)
     eps2, h2 = 1e-3, 0.03
     ref = with_xp(orc, jm, oracle_eval(orc, jm, slots, eps2, h2))
     sess.load(jm)
