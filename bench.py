@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--no-neighbour-lists", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target oracle time of the CPU baseline")
     ap.add_argument("--shape", default=None, help="i_per_group,j_splits override")
+    ap.add_argument("--sweep", default=None,
+                    help="comma-separated k: also time active blocks of 2^k against all N (DS and FP64)")
     return ap.parse_args()
 
 
@@ -226,6 +228,52 @@ def main():
     for v in variants.values():
         v.pop("res", None)
 
+    sweep = None
+    if args.sweep:
+        sweep = []
+        for k in (int(q) for q in args.sweep.split(",")):
+            nk = 2 ** k
+            sk = workloads.active_set(n, nk, seed=3)
+            t_islot = torch.tensor(sk, device=dev)
+            t_xi = t["x"][t_islot.long()].contiguous()
+            t_vi = t["v"][t_islot.long()].contiguous()
+            t_h2 = torch.full((nk,), h2, dtype=torch.float64, device=dev)
+            o = [torch.empty((nk, 3), dtype=torch.float64, device=dev) for _ in range(2)]
+            o += [torch.empty(nk, dtype=torch.float64, device=dev), torch.empty(nk, dtype=torch.int32, device=dev),
+                  torch.empty(nk, dtype=torch.float64, device=dev)]
+            entry = dict(k=k, ni=nk)
+            for variant in ("ds", "fp64"):
+                g6.check(hid, g6.g6mi_set_precision(hid, variant))
+                reps = max(3, min(50, int(2 ** 24 // max(1, nk))))
+                def calls(count):
+                    for _ in range(count):
+                        g6.check(hid, g6.g6mi_calc_device(hid, n, nk, t_islot, t_xi, t_vi, eps2, t_h2, *o,
+                                                          stream=stream))
+                with torch.cuda.stream(stream):
+                    calls(2)
+                    torch.cuda.synchronize()
+                    # whole steps, without per-kernel events
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    calls(reps)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    ms = e0.elapsed_time(e1) / reps
+                    # per-kernel times in a separate pass
+                    g6.check(hid, g6.g6mi_enable_timing(hid, 1))
+                    calls(reps)
+                    torch.cuda.synchronize()
+                tot = g6.g6mi_timing_totals(hid)
+                g6.check(hid, g6.g6mi_enable_timing(hid, 0))
+                entry[variant] = dict(ms_per_step=round(ms, 4), force_ms=round(tot["force_ms"] / tot["count"], 4),
+                                      predict_ms=round(tot["predict_ms"] / tot["count"], 4),
+                                      reduce_ms=round(tot["reduce_ms"] / tot["count"], 4),
+                                      pairs_per_s=float(nk) * n / (ms * 1e-3),
+                                      shape=g6.g6mi_get_shape(hid))
+            log(f"[bench] sweep k={k}: ds {entry['ds']['ms_per_step']} ms, fp64 {entry['fp64']['ms_per_step']} ms")
+            sweep.append(entry)
+
     line = dict(
         metric=METRIC, value=value, unit="pairs/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
         ms_per_step=round(main_run["ms_per_step"], 4), higher_is_better=True, scaling="weak",
@@ -237,7 +285,7 @@ def main():
                     parallelism="single-gpu"),
         kernel_ms=dict(predict=round(main_run["predict_ms"], 4), force=round(main_run["force_ms"], 4),
                        reduce=round(main_run["reduce_ms"], 4)),
-        roofline=roofline, variants=variants, accuracy=accuracy, cpu_baseline=cpu,
+        roofline=roofline, variants=variants, accuracy=accuracy, cpu_baseline=cpu, sweep=sweep,
         device=dict(compute_units=info["compute_units"], clock_mhz=info["clock_mhz"],
                     name=torch.cuda.get_device_name(0)),
     )

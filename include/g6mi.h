@@ -110,6 +110,17 @@ int g6_set_j_particle(int id, int address, int index, double tj, double dtj,
                       double mass, const double k18[3], const double j6[3],
                       const double a2[3], const double v[3], const double x[3]);
 
+/* g6_set_j_particle for n records at once: record k goes to slot
+ * address[k] with particle index index[k], time tj[k], mass[k] and the
+ * row-major [n][3] arrays j6 (= jerk/6), a2 (= a/2), v and x.  dtj may be
+ * NULL (it is ignored, as in g6_set_j_particle).  All records are checked
+ * before any is stored.  Returns 0, G6MI_EINVAL or G6MI_ESTATE. */
+int g6mi_set_j_particles(int id, int n, const int address[], const int index[],
+                         const double tj[], const double dtj[],
+                         const double mass[], const double j6[][3],
+                         const double a2[][3], const double v[][3],
+                         const double x[][3]);
+
 /* Set the time t_i to which the next calculation predicts the j-particles
  * (tau_j = t_i - t_j in Eq. (1)-(2)). */
 void g6_set_ti(int id, double ti);
@@ -157,18 +168,21 @@ int g6calc_lasthalf2(int id, int nj, int ni, const int index[],
 int g6_nearest_neighbour(int id, int ni, int nnbindex[], double r2nn[]);
 
 /* Copy the neighbour lists of the last completed calculation to the host.
- * Returns 0, 1 if any i-particle had more than G6MI_NB_MAX neighbours, or a
- * negative error code. */
+ * When some i-particle had more than G6MI_NB_MAX neighbours, its list is
+ * first rebuilt on the GPU from the G6MI_NB_MAX smallest indices (this reads
+ * the calculation's i-block again: after g6mi_calc_device its device buffers
+ * must still be valid).  Returns 0, 1 if any list overflowed, or a negative
+ * error code. */
 int g6_read_neighbour_list(int id);
 
 /* Neighbour list of i-particle `ipipe` (0-based position in the last
  * calculation's i-block): particle indices in ascending order.  Writes
  * *nblen = the true number of neighbours and the first
- * min(*nblen, maxlength, G6MI_NB_MAX) indices to nbl.  Returns 0, 1 if the
- * list was cut by maxlength or G6MI_NB_MAX, or a negative error code
- * (G6MI_ESTATE if g6_read_neighbour_list was not called after the
- * calculation).  When a list overflowed G6MI_NB_MAX, which G6MI_NB_MAX of
- * the neighbours are stored is not specified. */
+ * min(*nblen, maxlength, G6MI_NB_MAX) indices to nbl.  A list with more
+ * than G6MI_NB_MAX neighbours stores the G6MI_NB_MAX smallest particle
+ * indices.  Returns 0, 1 if the list was cut by maxlength or G6MI_NB_MAX, or
+ * a negative error code (G6MI_ESTATE if g6_read_neighbour_list was not
+ * called after the calculation). */
 int g6_get_neighbour_list(int id, int ipipe, int maxlength, int *nblen,
                           int nbl[]);
 

@@ -45,6 +45,7 @@ _SIGS = {
     "g6_set_tunit": (None, [_i]),
     "g6_set_xunit": (None, [_i]),
     "g6_set_j_particle": (_i, [_i, _i, _i, _d, _d, _d, _D, _D, _D, _D, _D]),
+    "g6mi_set_j_particles": (_i, [_i, _i, _I, _I, _D, _D, _D, _D, _D, _D, _D]),
     "g6_set_ti": (None, [_i, _d]),
     "g6calc_firsthalf": (_i, [_i, _i, _i, _I, _D, _D, _D, _D, _D, _d, _D]),
     "g6calc_lasthalf": (_i, [_i, _i, _i, _I, _D, _D, _d, _D, _D, _D, _D]),
@@ -73,6 +74,14 @@ def _L():
     """The loaded libg6mi.so with its signatures declared."""
     global _lib
     if _lib is None:
+        # One HIP runtime per process: PyTorch ships its own libamdhip64 with
+        # the same soname as /opt/rocm's.  Whichever is loaded first serves
+        # both, so load torch's first; torch's device pointers and streams
+        # are then valid in this library.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_0902_4463_amd.build`")
         lib = ctypes.CDLL(LIB_PATH)
@@ -164,6 +173,16 @@ def g6_set_j_particle(id, address, index, tj, dtj, mass, k18, j6, a2, v, x) -> i
     k18, j6, a2, v, x = (_f64(q, (3,)) for q in (k18, j6, a2, v, x))
     return _L().g6_set_j_particle(id, int(address), int(index), float(tj), float(dtj),
                                   float(mass), _pd(k18), _pd(j6), _pd(a2), _pd(v), _pd(x))
+
+
+def g6mi_set_j_particles(id, n, address, index, tj, dtj, mass, j6, a2, v, x) -> int:
+    """Bulk g6_set_j_particle: n records from arrays (vectors as (n, 3))."""
+    address, index = _i32(address), _i32(index)
+    tj, mass = _f64(tj, (n,)), _f64(mass, (n,))
+    j6, a2, v, x = (_f64(q, (n, 3)) for q in (j6, a2, v, x))
+    dtj = None if dtj is None else _f64(dtj, (n,))
+    return _L().g6mi_set_j_particles(id, int(n), _pi(address), _pi(index), _pd(tj), _pd(dtj), _pd(mass),
+                                     _pd(j6), _pd(a2), _pd(v), _pd(x))
 
 
 def g6_set_ti(id: int, ti: float) -> None:
@@ -300,11 +319,9 @@ class Session:
         self.close()
 
     def load(self, jm) -> None:
-        """Store every slot of a ``workloads.JMemory`` with g6_set_j_particle."""
-        zero = np.zeros(3)
-        for k in range(jm.n):
-            check(self.id, g6_set_j_particle(self.id, k, int(jm.index[k]), jm.t[k], 0.0, jm.m[k],
-                                             zero, jm.j6[k], jm.a2[k], jm.v[k], jm.x[k]))
+        """Store every slot of a ``workloads.JMemory`` (bulk g6_set_j_particle)."""
+        check(self.id, g6mi_set_j_particles(self.id, jm.n, np.arange(jm.n), jm.index, jm.t, None, jm.m,
+                                            jm.j6, jm.a2, jm.v, jm.x))
 
     def calc(self, nj, ti, index, xi, vi, eps2, h2, neighbours=True):
         ni = len(index)

@@ -108,7 +108,7 @@ struct Handle {
   PinBuf h_i, h_out;
 
   // work buffers
-  DevBuf d_part, d_nnr2, d_nnslot, d_nbcount, d_nblist, d_flags;
+  DevBuf d_part, d_nnr2, d_nnslot, d_nbcount, d_nblist, d_flags, d_ovf;
 
   // calculation state
   bool pending = false;
@@ -117,11 +117,15 @@ struct Handle {
   double c_eps2 = 0.0;
   std::vector<int> c_index;
   hipStream_t c_stream = nullptr;
+  ForceArgs c_args;        // interaction arguments of the last calculation
+  int c_prec = G6MI_PREC_DS;
+  bool c_nbl = true;
   bool c_have = false;     // a calculation was enqueued and not superseded
   bool res_valid = false;  // host results of the last host-path calc
   std::vector<int> r_nnb;
   std::vector<double> r_r2nn;
   bool nb_read = false;
+  bool nb_exact_done = false; // overflow pass run for the last calculation
   std::vector<int> r_nbcount, r_nblist;
 
   // timing: one set of four events per timed calculation since the last
@@ -312,8 +316,8 @@ int enqueue_calc(Handle &h, int nj, int ni, const int *d_islot, const double *d_
   HIPCHK(&h, ensure(h.d_nbcount, n * sizeof(int)));
   HIPCHK(&h, ensure(h.d_nblist, n * kNbMax * sizeof(int)));
   HIPCHK(&h, ensure(h.d_flags, 64));
-  int *flags = static_cast<int *>(h.d_flags.p);
-  HIPCHK(&h, hipMemsetAsync(flags, 0, sizeof(int), s));
+  HIPCHK(&h, ensure(h.d_ovf, n * sizeof(int)));
+  int *status = static_cast<int *>(h.d_flags.p); // zeroed by the predictor launch
 
   h.shape[0] = ipw;
   h.shape[1] = nsplit;
@@ -330,7 +334,7 @@ int enqueue_calc(Handle &h, int nj, int ni, const int *d_islot, const double *d_
   }
   if (ev) HIPCHK(&h, hipEventRecord(ev[0], s));
   HIPCHK(&h, launch_predict(h.prec, nj, h.ti, h.jm, h.d_pred.p,
-                            static_cast<int *>(h.d_nbcount.p), ni, s));
+                            static_cast<int *>(h.d_nbcount.p), ni, status, s));
   if (ev) HIPCHK(&h, hipEventRecord(ev[1], s));
   ForceArgs a;
   a.jpred = h.d_pred.p;
@@ -351,7 +355,8 @@ int enqueue_calc(Handle &h, int nj, int ni, const int *d_islot, const double *d_
   HIPCHK(&h, launch_force(h.prec, h.nbl, a, nsplit, s));
   if (ev) HIPCHK(&h, hipEventRecord(ev[2], s));
   HIPCHK(&h, launch_reduce(nsplit, ni, a.part, a.nn_r2, a.nn_slot, h.jm.index, a.nb_count,
-                           a.nb_slot, h.nbl, d_acc, d_jerk, d_pot, d_nnb, d_r2nn, flags, s));
+                           a.nb_slot, h.nbl, d_acc, d_jerk, d_pot, d_nnb, d_r2nn, status,
+                           static_cast<int *>(h.d_ovf.p), s));
   if (ev) {
     HIPCHK(&h, hipEventRecord(ev[3], s));
     ++h.n_timed;
@@ -360,8 +365,12 @@ int enqueue_calc(Handle &h, int nj, int ni, const int *d_islot, const double *d_
   h.c_ni = ni;
   h.c_eps2 = eps2;
   h.c_stream = s;
+  h.c_args = a;
+  h.c_prec = h.prec;
+  h.c_nbl = h.nbl;
   h.c_have = true;
   h.nb_read = false;
+  h.nb_exact_done = false;
   return 0;
 }
 
@@ -528,7 +537,8 @@ G6MI_API int g6_close(int id) {
   (void)hipStreamSynchronize(h->stream);
   if (h->c_stream && h->c_stream != h->stream) (void)hipStreamSynchronize(h->c_stream);
   for (DevBuf *b : {&h->d_jm, &h->d_pred, &h->d_stage, &h->d_i, &h->d_out, &h->d_part,
-                    &h->d_nnr2, &h->d_nnslot, &h->d_nbcount, &h->d_nblist, &h->d_flags})
+                    &h->d_nnr2, &h->d_nnslot, &h->d_nbcount, &h->d_nblist, &h->d_flags,
+                    &h->d_ovf})
     b->release();
   for (PinBuf *b : {&h->h_stage, &h->h_i, &h->h_out}) b->release();
   for (auto &q : h->evs)
@@ -550,18 +560,21 @@ G6MI_API int g6_npipes(void) {
 G6MI_API void g6_set_tunit(int) {}
 G6MI_API void g6_set_xunit(int) {}
 
-G6MI_API int g6_set_j_particle(int id, int address, int index, double tj, double dtj,
-                               double mass, const double k18[3], const double j6[3],
-                               const double a2[3], const double v[3], const double x[3]) {
-  (void)dtj;
-  (void)k18;
-  Handle *h = get_open(id);
-  if (!h) return code_for_missing(id);
+namespace {
+int check_j(Handle *h, int address, double tj, double mass, const double *j6, const double *a2,
+            const double *v, const double *x) {
   if (address < 0 || address >= G6MI_NJ_MAX) return fail(h, G6MI_EINVAL, "address out of range");
   if (!j6 || !a2 || !v || !x) return fail(h, G6MI_EINVAL, "null j-particle array");
   if (!std::isfinite(tj) || !std::isfinite(mass) || !finite3(x) || !finite3(v) || !finite3(a2) ||
       !finite3(j6))
     return fail(h, G6MI_EINVAL, "non-finite j-particle data");
+  return 0;
+}
+
+// Stage one checked record in the host master copy (uploaded by the next
+// calculation).
+void store_j(Handle *h, int address, int index, double tj, double mass, const double *j6,
+             const double *a2, const double *v, const double *x) {
   grow_host(*h, static_cast<size_t>(address) + 1);
   double *r = &h->h_rec[static_cast<size_t>(address) * kRecDoubles];
   r[0] = tj;
@@ -584,6 +597,37 @@ G6MI_API int g6_set_j_particle(int id, int address, int index, double tj, double
   h->h_set[address] = 1;
   while (h->n_contig < h->h_set.size() && h->h_set[h->n_contig]) ++h->n_contig;
   mark_dirty(*h, address);
+}
+} // namespace
+
+G6MI_API int g6_set_j_particle(int id, int address, int index, double tj, double dtj,
+                               double mass, const double k18[3], const double j6[3],
+                               const double a2[3], const double v[3], const double x[3]) {
+  (void)dtj;
+  (void)k18;
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  const int rc = check_j(h, address, tj, mass, j6, a2, v, x);
+  if (rc) return rc;
+  store_j(h, address, index, tj, mass, j6, a2, v, x);
+  return G6MI_OK;
+}
+
+G6MI_API int g6mi_set_j_particles(int id, int n, const int address[], const int index[],
+                                  const double tj[], const double dtj[], const double mass[],
+                                  const double j6[][3], const double a2[][3], const double v[][3],
+                                  const double x[][3]) {
+  (void)dtj;
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  if (n < 0) return fail(h, G6MI_EINVAL, "negative record count");
+  if (n > 0 && (!address || !index || !tj || !mass || !j6 || !a2 || !v || !x))
+    return fail(h, G6MI_EINVAL, "null j-particle array");
+  for (int k = 0; k < n; ++k) {
+    const int rc = check_j(h, address[k], tj[k], mass[k], j6[k], a2[k], v[k], x[k]);
+    if (rc) return rc;
+  }
+  for (int k = 0; k < n; ++k) store_j(h, address[k], index[k], tj[k], mass[k], j6[k], a2[k], v[k], x[k]);
   return G6MI_OK;
 }
 
@@ -653,6 +697,18 @@ G6MI_API int g6_read_neighbour_list(int id) {
   HIPCHK(h, hipSetDevice(h->device));
   HIPCHK(h, hipStreamSynchronize(h->c_stream));
   const size_t n = static_cast<size_t>(h->c_ni);
+  if (n > 0 && h->c_nbl) {
+    // overflowed lists: keep the G6MI_NB_MAX smallest indices (exact pass)
+    int status[kStatusWords] = {0, 0};
+    HIPCHK(h, hipMemcpy(status, h->d_flags.p, sizeof(status), hipMemcpyDeviceToHost));
+    if (status[kStatusOverflowCount] > 0 && !h->nb_exact_done) {
+      HIPCHK(h, launch_nb_exact(h->c_prec, h->c_args, h->jm.index, static_cast<int *>(h->d_flags.p),
+                                static_cast<int *>(h->d_ovf.p), status[kStatusOverflowCount],
+                                h->c_stream));
+      HIPCHK(h, hipStreamSynchronize(h->c_stream));
+      h->nb_exact_done = true;
+    }
+  }
   h->r_nbcount.assign(n, 0);
   h->r_nblist.assign(n * kNbMax, -1);
   if (n > 0) {

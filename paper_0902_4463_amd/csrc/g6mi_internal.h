@@ -20,12 +20,19 @@ namespace g6mi {
 #define G6MI_GROUP_UNROLL 2 // groups per unrolled loop body
 #endif
 #ifndef G6MI_WIDE_WAVES
-#define G6MI_WIDE_WAVES 4 // register budget of the wide kernel: waves per SIMD (0: free)
+#define G6MI_WIDE_WAVES 3 // register budget of the wide kernel: waves per SIMD (0: free)
 #endif
 
 constexpr int kWG = 256;          // lanes per workgroup: four wave64
 constexpr int kTile = G6MI_TILE;  // j-records staged in LDS per tile
 constexpr int kNbMax = 256;       // neighbour slots per i-particle
+
+// Status words of one calculation in device memory (zeroed by the predictor
+// launch): flags (bit 0 non-finite output, bit 1 neighbour overflow) and the
+// number of i-particles queued for the exact overflow pass.
+constexpr int kStatusFlags = 0;
+constexpr int kStatusOverflowCount = 1;
+constexpr int kStatusWords = 2;
 
 // Predicted j-record sizes in bytes, one record per j-slot:
 //   DS   : float4{x_hi, m}, float4{x_lo, 0}, float4{v, 0}  = 48 B
@@ -63,7 +70,8 @@ struct ForceArgs {
 };
 
 hipError_t launch_predict(int prec, int nj, double ti, const JMem &jm,
-                          void *out, int *nb_count, int ni, hipStream_t s);
+                          void *out, int *nb_count, int ni, int *status,
+                          hipStream_t s);
 
 hipError_t launch_force(int prec, bool nbl, const ForceArgs &a, int nsplit,
                         hipStream_t s);
@@ -72,7 +80,14 @@ hipError_t launch_reduce(int nsplit, int ni, const double *part,
                          const double *nn_r2, const int *nn_slot,
                          const int *jindex, int *nb_count, int *nb_slot,
                          bool nbl, double *acc, double *jerk, double *pot,
-                         int *nnb, double *r2nn, int *flags, hipStream_t s);
+                         int *nnb, double *r2nn, int *status, int *ovf_list,
+                         hipStream_t s);
+
+// Rebuild the lists of the novf overflowed i-particles queued by the
+// reduction (see reduce_kernel) with the kNbMax smallest indices.
+hipError_t launch_nb_exact(int prec, const ForceArgs &a, const int *jindex,
+                           const int *status, const int *ovf_list, int novf,
+                           hipStream_t s);
 
 // Scatter nd staged records into the j-memory.  rec is [nd][16] doubles:
 // t, m, x[3], v[3], a2[3], j6[3], index (as double), pad; slots is [nd].

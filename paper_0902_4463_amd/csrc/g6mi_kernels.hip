@@ -23,6 +23,12 @@
 
 namespace g6mi {
 
+// j-records per group: the unit of the nearest-neighbour bookkeeping, of the
+// neighbour-list flags and of the first level of float32 summation.
+constexpr int kGroup = G6MI_GROUP;
+static_assert(kTile / kGroup <= 32, "one mask bit per group");
+static_assert(kTile % kGroup == 0, "whole groups per tile");
+
 size_t pred_record_bytes(int prec) {
   switch (prec) {
   case G6MI_PREC_FP32: return 32;
@@ -43,9 +49,10 @@ __global__ __launch_bounds__(256) void predict_kernel(
     const double *__restrict__ m, const double *__restrict__ x,
     const double *__restrict__ v, const double *__restrict__ a2,
     const double *__restrict__ j6, size_t cap, void *__restrict__ out,
-    int *__restrict__ nb_count, int ni) {
+    int *__restrict__ nb_count, int ni, int *__restrict__ status) {
   const int k = blockIdx.x * 256 + threadIdx.x;
   if (k < ni) nb_count[k] = 0; // fresh neighbour counters for this call
+  if (k < kStatusWords) status[k] = 0;
   if (k >= nj) return;
   const double tau = ti - t[k];
   double xp[3], vp[3];
@@ -103,251 +110,48 @@ __device__ __forceinline__ double rsqrt_f64(double s) {
   return y;
 }
 
-// Per-lane state of one i-particle.  FP32/DS sum each tile in float32
-// (t*), then add the tile sums into float64 totals (d*); FP64 sums in
-// float64 directly.
+// Per-lane position and velocity of one i-particle.
 template <int PREC> struct IState;
 
 template <> struct IState<G6MI_PREC_DS> {
   float xh[3], xl[3], v[3];
-  float ta[3], tj1[3], tj2[3], tp;
 };
 template <> struct IState<G6MI_PREC_FP32> {
   float x[3], v[3];
-  float ta[3], tj1[3], tj2[3], tp;
 };
 template <> struct IState<G6MI_PREC_FP64> {
   double x[3], v[3];
-  double ta[3], tj1[3], tj2[3], tp;
+};
+
+// Running sums of one i-particle's pair terms: acceleration, the two jerk
+// parts (m w / r^3 and m (r.w) r / r^5) and m / r.
+//
+// Float32 variants sum in two levels before the float64 totals: a fresh
+// group of kGroup pairs, then the group sums into the tile sums.  A close
+// neighbour's term can exceed the far-field terms by 10^4 or more; added one
+// by one to a partial sum holding it, terms below half its ulp would round
+// away entirely, a systematic loss up to ~1e-5.  Within a group at most
+// kGroup - 1 terms meet such a partial, and group sums are large enough to
+// round rather than vanish.
+template <class R> struct Sums {
+  R a[3], j1[3], j2[3], p;
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a[k] = j1[k] = j2[k] = R(0);
+    p = R(0);
+  }
+  __device__ __forceinline__ void add(const Sums &o) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      a[k] += o.a[k];
+      j1[k] += o.j1[k];
+      j2[k] += o.j2[k];
+    }
+    p += o.p;
+  }
 };
 
 template <int PREC> using real_t = std::conditional_t<PREC == G6MI_PREC_FP64, double, float>;
-
-// One pair (i, j).  MASK: compare the j-slot with the i-particle's own slot
-// and drop the self pair.  NBL: build neighbour lists.
-template <int PREC, bool MASK, bool NBL>
-__device__ __forceinline__ void pair(IState<PREC> &st, const float4 *__restrict__ rec,
-                                     int jslot, int islot, real_t<PREC> eps2,
-                                     real_t<PREC> h2, real_t<PREC> &best, int &bslot,
-                                     int *__restrict__ nb_count, int *__restrict__ nb_row) {
-  using R = real_t<PREC>;
-  R dx, dy, dz, dvx, dvy, dvz, mj;
-  if constexpr (PREC == G6MI_PREC_DS) {
-    const float4 p = rec[0], q = rec[1], w = rec[2];
-    // Eq. (3): separation of two DS numbers, 3 float32 operations
-    dx = (p.x - st.xh[0]) + (q.x - st.xl[0]);
-    dy = (p.y - st.xh[1]) + (q.y - st.xl[1]);
-    dz = (p.z - st.xh[2]) + (q.z - st.xl[2]);
-    dvx = w.x - st.v[0];
-    dvy = w.y - st.v[1];
-    dvz = w.z - st.v[2];
-    mj = p.w;
-  } else if constexpr (PREC == G6MI_PREC_FP32) {
-    const float4 p = rec[0], w = rec[1];
-    dx = p.x - st.x[0];
-    dy = p.y - st.x[1];
-    dz = p.z - st.x[2];
-    dvx = w.x - st.v[0];
-    dvy = w.y - st.v[1];
-    dvz = w.z - st.v[2];
-    mj = p.w;
-  } else {
-    const double2 *r2 = reinterpret_cast<const double2 *>(rec);
-    const double2 p0 = r2[0], p1 = r2[1], w0 = r2[2], w1 = r2[3];
-    dx = p0.x - st.x[0];
-    dy = p0.y - st.x[1];
-    dz = p1.x - st.x[2];
-    dvx = w0.x - st.v[0];
-    dvy = w0.y - st.v[1];
-    dvz = w1.x - st.v[2];
-    mj = p1.y;
-  }
-  R r2u = dx * dx + dy * dy + dz * dz;
-  R s = r2u + eps2;
-  if constexpr (MASK) {
-    const bool self = (jslot == islot);
-    mj = self ? R(0) : mj;
-    s = self ? R(1) : s;
-    r2u = self ? R(INFINITY) : r2u;
-  }
-  R rinv;
-  if constexpr (PREC == G6MI_PREC_FP64) rinv = rsqrt_f64(s);
-  else rinv = __builtin_amdgcn_rsqf(s);
-  const R rinv2 = rinv * rinv;
-  const R mr = mj * rinv;          // m / r
-  const R mr3 = mr * rinv2;        // m / r^3
-  const R rv = dx * dvx + dy * dvy + dz * dvz;
-  const R mr3t = mr3 * (rv * rinv2); // m (r.v) / r^5
-  st.tp += mr;
-  st.ta[0] += mr3 * dx;
-  st.ta[1] += mr3 * dy;
-  st.ta[2] += mr3 * dz;
-  st.tj1[0] += mr3 * dvx;
-  st.tj1[1] += mr3 * dvy;
-  st.tj1[2] += mr3 * dvz;
-  st.tj2[0] += mr3t * dx;
-  st.tj2[1] += mr3t * dy;
-  st.tj2[2] += mr3t * dz;
-  if (r2u < best) { // strict: the first (lowest) slot wins a tie
-    best = r2u;
-    bslot = jslot;
-  }
-  if constexpr (NBL) {
-    if (r2u < h2) {
-      const int pos = atomicAdd(nb_count, 1);
-      if (pos < kNbMax) nb_row[pos] = jslot;
-    }
-  }
-}
-
-// Grid: x = i-blocks of ipw i-particles, y = j-splits.  Lane tid handles
-// i-particle (tid mod ipw) of the block and j-records sub, sub + L, ...
-// of every tile, with sub = tid / ipw and L = 256 / ipw lanes per
-// i-particle.  With ipw >= 64 all lanes of a wave read the same j-record
-// (an LDS broadcast).  The L lanes of one i-particle are summed in a fixed
-// order at the end.
-template <int PREC, bool NBL>
-__global__ __launch_bounds__(kWG) void force_kernel(ForceArgs a) {
-  using R = real_t<PREC>;
-  constexpr int REC = rec4<PREC>();
-  constexpr int kTileF4 = kTile * REC;
-  constexpr int kRedBytes = kWG * 9 * 8; // 7 sums + r2 + slot per lane
-  constexpr int kTileBytes = kTileF4 * 16;
-  constexpr int kLdsBytes = kRedBytes > kTileBytes ? kRedBytes : kTileBytes;
-  __shared__ __attribute__((aligned(16))) unsigned char lds[kLdsBytes];
-  float4 *tile = reinterpret_cast<float4 *>(lds);
-
-  const int tid = threadIdx.x;
-  const int ipw = a.ipw;
-  const int L = kWG >> a.log2ipw;
-  const int il = tid & (ipw - 1);
-  const int sub = tid >> a.log2ipw;
-  const int i = blockIdx.x * ipw + il;
-  const bool ivalid = i < a.ni;
-
-  IState<PREC> st;
-  int islot = -1;
-  R h2 = R(-INFINITY);
-  {
-    double xi[3] = {0.0, 0.0, 0.0}, vi[3] = {0.0, 0.0, 0.0};
-    if (ivalid) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        xi[d] = a.xi[3 * static_cast<size_t>(i) + d];
-        vi[d] = a.vi[3 * static_cast<size_t>(i) + d];
-      }
-      islot = a.islot[i];
-      h2 = static_cast<R>(a.h2[i]);
-    }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      if constexpr (PREC == G6MI_PREC_DS) {
-        st.xh[d] = static_cast<float>(xi[d]);
-        st.xl[d] = static_cast<float>(xi[d] - static_cast<double>(st.xh[d]));
-        st.v[d] = static_cast<float>(vi[d]);
-      } else {
-        st.x[d] = static_cast<R>(xi[d]);
-        st.v[d] = static_cast<R>(vi[d]);
-      }
-      st.ta[d] = st.tj1[d] = st.tj2[d] = R(0);
-    }
-    st.tp = R(0);
-  }
-  const R eps2 = static_cast<R>(a.eps2);
-  double acc[3] = {0.0, 0.0, 0.0}, jrk[3] = {0.0, 0.0, 0.0}, pot = 0.0;
-  R best = R(INFINITY);
-  int bslot = -1;
-  int *nb_cnt = a.nb_count + (ivalid ? i : 0);
-  int *nb_row = a.nb_slot + static_cast<size_t>(ivalid ? i : 0) * kNbMax;
-
-  const int ntiles = (a.nj + kTile - 1) / kTile;
-  const int per = (ntiles + gridDim.y - 1) / gridDim.y;
-  const int t0 = blockIdx.y * per;
-  const int t1 = min(ntiles, t0 + per);
-  const float4 *jp = static_cast<const float4 *>(a.jpred);
-
-  for (int tt = t0; tt < t1; ++tt) {
-    const int jbase = tt * kTile;
-    const int cnt = min(kTile, a.nj - jbase);
-    __syncthreads();
-    {
-      const float4 *src = jp + static_cast<size_t>(jbase) * REC;
-      const int n4 = cnt * REC;
-      for (int q = tid; q < n4; q += kWG) tile[q] = src[q];
-    }
-    __syncthreads();
-    const bool self_here = islot >= jbase && islot < jbase + cnt;
-    if (__any(self_here)) {
-      for (int jj = sub; jj < cnt; jj += L)
-        pair<PREC, true, NBL>(st, tile + jj * REC, jbase + jj, islot, eps2, h2,
-                              best, bslot, nb_cnt, nb_row);
-    } else if (cnt == kTile && L == 1) {
-#pragma unroll 4
-      for (int jj = 0; jj < kTile; ++jj)
-        pair<PREC, false, NBL>(st, tile + jj * REC, jbase + jj, islot, eps2,
-                               h2, best, bslot, nb_cnt, nb_row);
-    } else {
-      for (int jj = sub; jj < cnt; jj += L)
-        pair<PREC, false, NBL>(st, tile + jj * REC, jbase + jj, islot, eps2,
-                               h2, best, bslot, nb_cnt, nb_row);
-    }
-    // fold the tile sums into the float64 totals
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      acc[d] += static_cast<double>(st.ta[d]);
-      jrk[d] += static_cast<double>(st.tj1[d]) - 3.0 * static_cast<double>(st.tj2[d]);
-      st.ta[d] = st.tj1[d] = st.tj2[d] = R(0);
-    }
-    pot += static_cast<double>(st.tp);
-    st.tp = R(0);
-  }
-
-  double bestd = static_cast<double>(best);
-  if (L > 1) {
-    __syncthreads();
-    double *red = reinterpret_cast<double *>(lds); // [9][kWG]
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      red[d * kWG + tid] = acc[d];
-      red[(3 + d) * kWG + tid] = jrk[d];
-    }
-    red[6 * kWG + tid] = pot;
-    red[7 * kWG + tid] = bestd;
-    reinterpret_cast<int *>(red + 8 * kWG)[tid] = bslot;
-    __syncthreads();
-    if (sub == 0) {
-      for (int q = 1; q < L; ++q) {
-        const int o = q * ipw + il;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          acc[d] += red[d * kWG + o];
-          jrk[d] += red[(3 + d) * kWG + o];
-        }
-        pot += red[6 * kWG + o];
-        const double r2o = red[7 * kWG + o];
-        const int so = reinterpret_cast<const int *>(red + 8 * kWG)[o];
-        if (r2o < bestd || (r2o == bestd && so >= 0 && (bslot < 0 || so < bslot))) {
-          bestd = r2o;
-          bslot = so;
-        }
-      }
-    }
-  }
-  if (sub == 0 && ivalid) {
-    const size_t ni = static_cast<size_t>(a.ni);
-    double *p = a.part + static_cast<size_t>(blockIdx.y) * 7 * ni + i;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      p[d * ni] = acc[d];
-      p[(3 + d) * ni] = jrk[d];
-    }
-    p[6 * ni] = pot;
-    a.nn_r2[blockIdx.y * ni + i] = bestd;
-    a.nn_slot[blockIdx.y * ni + i] = bslot;
-  }
-}
-
-// ------------------------------------------------- interaction, wide blocks
 
 // Separation of i and one j-record: r = x_j - x_i (Eq. (3) for DS), the
 // velocity difference and r^2 without softening.
@@ -385,23 +189,82 @@ __device__ __forceinline__ void separation(const IState<PREC> &st, const float4 
   }
 }
 
+// r^2 in one fixed expression, so that every path takes the same neighbour
+// decisions for the same pair
+template <int PREC>
+__device__ __forceinline__ real_t<PREC> sq3(const real_t<PREC> d[3]) {
+  return fma(d[2], d[2], fma(d[1], d[1], d[0] * d[0]));
+}
+
 template <int PREC>
 __device__ __forceinline__ real_t<PREC> r2_of(const IState<PREC> &st, const float4 *__restrict__ rec) {
   real_t<PREC> d[3], w[3], mj;
   separation<PREC>(st, rec, d, w, mj);
-  return d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  return sq3<PREC>(d);
 }
 
-// The pair terms of Sec. 2.3 added to the tile sums; returns r^2 (without
-// softening) for the neighbour search.  No self test: the caller only uses
-// it on tiles that hold neither i-particle's own slot.
-template <int PREC>
-__device__ __forceinline__ real_t<PREC> pair_core(IState<PREC> &st, const float4 *__restrict__ rec,
-                                                  real_t<PREC> eps2) {
+// One pair (i, j).  MASK: compare the j-slot with the i-particle's own slot
+// and drop the self pair.  NBL: build neighbour lists.
+template <int PREC, bool MASK, bool NBL>
+__device__ __forceinline__ void pair(const IState<PREC> &st, Sums<real_t<PREC>> &acc,
+                                     const float4 *__restrict__ rec,
+                                     int jslot, int islot, real_t<PREC> eps2,
+                                     real_t<PREC> h2, real_t<PREC> &best, int &bslot,
+                                     int *__restrict__ nb_count, int *__restrict__ nb_row) {
   using R = real_t<PREC>;
   R d[3], w[3], mj;
   separation<PREC>(st, rec, d, w, mj);
-  const R r2u = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  const R dx = d[0], dy = d[1], dz = d[2], dvx = w[0], dvy = w[1], dvz = w[2];
+  R r2u = sq3<PREC>(d);
+  R s = r2u + eps2;
+  if constexpr (MASK) {
+    const bool self = (jslot == islot);
+    mj = self ? R(0) : mj;
+    s = self ? R(1) : s;
+    r2u = self ? R(INFINITY) : r2u;
+  }
+  R rinv;
+  if constexpr (PREC == G6MI_PREC_FP64) rinv = rsqrt_f64(s);
+  else rinv = __builtin_amdgcn_rsqf(s);
+  const R rinv2 = rinv * rinv;
+  const R mr = mj * rinv;          // m / r
+  const R mr3 = mr * rinv2;        // m / r^3
+  const R rv = dx * dvx + dy * dvy + dz * dvz;
+  const R mr3t = mr3 * (rv * rinv2); // m (r.v) / r^5
+  acc.p += mr;
+  acc.a[0] += mr3 * dx;
+  acc.a[1] += mr3 * dy;
+  acc.a[2] += mr3 * dz;
+  acc.j1[0] += mr3 * dvx;
+  acc.j1[1] += mr3 * dvy;
+  acc.j1[2] += mr3 * dvz;
+  acc.j2[0] += mr3t * dx;
+  acc.j2[1] += mr3t * dy;
+  acc.j2[2] += mr3t * dz;
+  if (r2u < best) { // strict: the first (lowest) slot wins a tie
+    best = r2u;
+    bslot = jslot;
+  }
+  if constexpr (NBL) {
+    if (r2u < h2) {
+      const int pos = atomicAdd(nb_count, 1);
+      if (pos < kNbMax) nb_row[pos] = jslot;
+    }
+  }
+}
+
+// ------------------------------------------------- interaction, wide blocks
+
+// The pair terms of Sec. 2.3 added to `acc`; returns r^2 (without
+// softening) for the neighbour search.  No self test: the caller only uses
+// it on tiles that hold neither i-particle's own slot.
+template <int PREC, bool FIRST = false>
+__device__ __forceinline__ real_t<PREC> pair_core(const IState<PREC> &st, Sums<real_t<PREC>> &acc,
+                                                  const float4 *__restrict__ rec, real_t<PREC> eps2) {
+  using R = real_t<PREC>;
+  R d[3], w[3], mj;
+  separation<PREC>(st, rec, d, w, mj);
+  const R r2u = sq3<PREC>(d);
   const R s = r2u + eps2;
   R rinv;
   if constexpr (PREC == G6MI_PREC_FP64) rinv = rsqrt_f64(s);
@@ -411,12 +274,22 @@ __device__ __forceinline__ real_t<PREC> pair_core(IState<PREC> &st, const float4
   const R mr3 = mr * rinv2;
   const R rv = d[0] * w[0] + d[1] * w[1] + d[2] * w[2];
   const R mr3t = mr3 * (rv * rinv2);
-  st.tp += mr;
+  if constexpr (FIRST) { // the group's first pair initialises its sums
+    acc.p = mr;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    st.ta[k] += mr3 * d[k];
-    st.tj1[k] += mr3 * w[k];
-    st.tj2[k] += mr3t * d[k];
+    for (int k = 0; k < 3; ++k) {
+      acc.a[k] = mr3 * d[k];
+      acc.j1[k] = mr3 * w[k];
+      acc.j2[k] = mr3t * d[k];
+    }
+  } else {
+    acc.p += mr;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      acc.a[k] += mr3 * d[k];
+      acc.j1[k] += mr3 * w[k];
+      acc.j2[k] += mr3t * d[k];
+    }
   }
   return r2u;
 }
@@ -447,9 +320,7 @@ __device__ __forceinline__ void load_i(IState<PREC> &st, const ForceArgs &a, int
       st.x[d] = static_cast<R>(xi[d]);
       st.v[d] = static_cast<R>(vi[d]);
     }
-    st.ta[d] = st.tj1[d] = st.tj2[d] = R(0);
   }
-  st.tp = R(0);
 }
 
 // Float64 running totals of one i-particle: the tile sums are folded in
@@ -458,17 +329,47 @@ struct Totals {
   double acc[3], jrk[3], pot;
 };
 
-template <int PREC>
-__device__ __forceinline__ void fold(IState<PREC> &st, Totals &t) {
+template <class R>
+__device__ __forceinline__ void fold(Sums<R> &ts, Totals &t) {
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    t.acc[d] += static_cast<double>(st.ta[d]);
-    t.jrk[d] += static_cast<double>(st.tj1[d]) - 3.0 * static_cast<double>(st.tj2[d]);
-    st.ta[d] = st.tj1[d] = st.tj2[d] = real_t<PREC>(0);
+    t.acc[d] += static_cast<double>(ts.a[d]);
+    t.jrk[d] += static_cast<double>(ts.j1[d]) - 3.0 * static_cast<double>(ts.j2[d]);
   }
-  t.pot += static_cast<double>(st.tp);
-  st.tp = real_t<PREC>(0);
+  t.pot += static_cast<double>(ts.p);
+  ts.zero();
 }
+
+// Per-pair path for tiles holding an own slot or the ragged end: the pair
+// terms go through group sums of kGroup pairs (float32 variants) before the
+// tile sums, as on the grouped path.
+template <int PREC, bool NBL>
+struct MaskedRun {
+  using R = real_t<PREC>;
+  Sums<R> g;
+  int n = 0;
+  __device__ __forceinline__ void start() {
+    g.zero();
+    n = 0;
+  }
+  __device__ __forceinline__ void step(const IState<PREC> &st, Sums<R> &ts, const float4 *rec, int jslot,
+                                       int islot, R eps2, R h2, R &best, int &bslot, int *nb_count,
+                                       int *nb_row) {
+    if constexpr (PREC == G6MI_PREC_FP64) {
+      pair<PREC, true, NBL>(st, ts, rec, jslot, islot, eps2, h2, best, bslot, nb_count, nb_row);
+    } else {
+      pair<PREC, true, NBL>(st, g, rec, jslot, islot, eps2, h2, best, bslot, nb_count, nb_row);
+      if (++n == kGroup) {
+        ts.add(g);
+        start();
+      }
+    }
+  }
+  __device__ __forceinline__ void finish(Sums<R> &ts) {
+    if constexpr (PREC != G6MI_PREC_FP64) ts.add(g);
+  }
+};
+
 
 __device__ __forceinline__ void nb_append(int *__restrict__ nb_count, int *__restrict__ nb_slot,
                                           int i, int jslot) {
@@ -490,18 +391,15 @@ __device__ __forceinline__ void nb_append(int *__restrict__ nb_count, int *__res
 // only such groups are re-examined.
 // Tiles that contain an i-particle's own slot, and the ragged last tile,
 // take the per-pair path with explicit self exclusion.
-constexpr int kGroup = G6MI_GROUP;
-static_assert(kTile / kGroup <= 32, "one mask bit per group");
-static_assert(kTile % kGroup == 0, "whole groups per tile");
 
-#if G6MI_WIDE_WAVES > 0
-#define G6MI_WIDE_BOUNDS __launch_bounds__(kWG, G6MI_WIDE_WAVES)
-#else
-#define G6MI_WIDE_BOUNDS __launch_bounds__(kWG)
-#endif
+// Register budget: G6MI_WIDE_WAVES waves per SIMD for the float32
+// variants; float64 state takes twice the registers, so one wave fewer.
+template <int PREC> constexpr int wide_waves() {
+  return G6MI_WIDE_WAVES <= 1 ? 1 : (PREC == G6MI_PREC_FP64 ? G6MI_WIDE_WAVES - 1 : G6MI_WIDE_WAVES);
+}
 
 template <int PREC, bool NBL>
-__global__ G6MI_WIDE_BOUNDS void force_wide(ForceArgs a) {
+__global__ __launch_bounds__(kWG, wide_waves<PREC>()) void force_wide(ForceArgs a) {
   using R = real_t<PREC>;
   constexpr int REC = rec4<PREC>();
   constexpr int kLoads = kTile * REC / kWG; // 16-byte loads per lane per tile
@@ -519,6 +417,9 @@ __global__ G6MI_WIDE_BOUNDS void force_wide(ForceArgs a) {
   load_i<PREC>(s1, a, i1, v1, slot1, h21);
   const R eps2 = static_cast<R>(a.eps2);
   Totals t0 = {{0, 0, 0}, {0, 0, 0}, 0}, t1 = {{0, 0, 0}, {0, 0, 0}, 0};
+  Sums<R> ts0, ts1; // tile sums
+  ts0.zero();
+  ts1.zero();
   // nearest neighbour: fast-path best r^2 and its group; exact path best
   R gbest0 = R(INFINITY), gbest1 = R(INFINITY);
   int grp0 = -1, grp1 = -1;
@@ -548,25 +449,42 @@ __global__ G6MI_WIDE_BOUNDS void force_wide(ForceArgs a) {
     __syncthreads();
     const bool self_here = (slot0 >= jbase && slot0 < jbase + cnt) || (slot1 >= jbase && slot1 < jbase + cnt);
     if (cnt < kTile || __any(self_here)) {
+      MaskedRun<PREC, NBL> r0, r1;
+      r0.start();
+      r1.start();
       for (int jj = 0; jj < cnt; ++jj) {
-        pair<PREC, true, NBL>(s0, tile + jj * REC, jbase + jj, slot0, eps2, h20, ebest0, eslot0,
-                              a.nb_count + (v0 ? i0 : 0),
-                              a.nb_slot + static_cast<size_t>(v0 ? i0 : 0) * kNbMax);
-        pair<PREC, true, NBL>(s1, tile + jj * REC, jbase + jj, slot1, eps2, h21, ebest1, eslot1,
-                              a.nb_count + (v1 ? i1 : 0),
-                              a.nb_slot + static_cast<size_t>(v1 ? i1 : 0) * kNbMax);
+        r0.step(s0, ts0, tile + jj * REC, jbase + jj, slot0, eps2, h20, ebest0, eslot0,
+                a.nb_count + (v0 ? i0 : 0), a.nb_slot + static_cast<size_t>(v0 ? i0 : 0) * kNbMax);
+        r1.step(s1, ts1, tile + jj * REC, jbase + jj, slot1, eps2, h21, ebest1, eslot1,
+                a.nb_count + (v1 ? i1 : 0), a.nb_slot + static_cast<size_t>(v1 ? i1 : 0) * kNbMax);
       }
+      r0.finish(ts0);
+      r1.finish(ts1);
     } else {
       // bit k of nbm0 / nbm1: group k holds a neighbour of i0 / i1
       unsigned nbm0 = 0u, nbm1 = 0u;
 #pragma unroll G6MI_GROUP_UNROLL
       for (int g = 0; g < kTile; g += kGroup) {
         R m0 = R(INFINITY), m1 = R(INFINITY);
+        if constexpr (PREC == G6MI_PREC_FP64) {
 #pragma unroll
-        for (int u = 0; u < kGroup; ++u) {
-          const float4 *rec = tile + (g + u) * REC;
-          m0 = fmin(m0, pair_core<PREC>(s0, rec, eps2));
-          m1 = fmin(m1, pair_core<PREC>(s1, rec, eps2));
+          for (int u = 0; u < kGroup; ++u) {
+            const float4 *rec = tile + (g + u) * REC;
+            m0 = fmin(m0, pair_core<PREC>(s0, ts0, rec, eps2));
+            m1 = fmin(m1, pair_core<PREC>(s1, ts1, rec, eps2));
+          }
+        } else {
+          Sums<R> g0, g1; // group sums, set by the group's first pair
+          m0 = pair_core<PREC, true>(s0, g0, tile + g * REC, eps2);
+          m1 = pair_core<PREC, true>(s1, g1, tile + g * REC, eps2);
+#pragma unroll
+          for (int u = 1; u < kGroup; ++u) {
+            const float4 *rec = tile + (g + u) * REC;
+            m0 = fmin(m0, pair_core<PREC>(s0, g0, rec, eps2));
+            m1 = fmin(m1, pair_core<PREC>(s1, g1, rec, eps2));
+          }
+          ts0.add(g0);
+          ts1.add(g1);
         }
         if (m0 < gbest0) {
           gbest0 = m0;
@@ -598,8 +516,8 @@ __global__ G6MI_WIDE_BOUNDS void force_wide(ForceArgs a) {
         }
       }
     }
-    fold<PREC>(s0, t0);
-    fold<PREC>(s1, t1);
+    fold(ts0, t0);
+    fold(ts1, t1);
   }
 
   // exact slot of the fast-path nearest neighbour: re-examine its group
@@ -633,19 +551,186 @@ __global__ G6MI_WIDE_BOUNDS void force_wide(ForceArgs a) {
   if (v1) store(i1, t1, ebest1, eslot1);
 }
 
+// Small blocks: ipw i-particles per workgroup (a power of two, at most 256)
+// and L = 256 / ipw lanes per i-particle.  Lane tid handles i-particle
+// (tid mod ipw) and records sub, sub + L, sub + 2L, ... of every tile, with
+// sub = tid / ipw: when the block is smaller than the workgroup the spare
+// lanes split the j-tile among themselves (Sec. 2.3, Fig. accMP1).  For
+// ipw >= 64 every lane of a wave reads the same record (an LDS broadcast).
+// Full tiles without an own slot use the grouped path of force_wide
+// (one min() per pair for the nearest neighbour, one neighbour bit per
+// group); the L lane sums of an i-particle are added in a fixed order.
+// Grid: x = i-blocks, y = j-splits.
+template <int PREC, bool NBL>
+__global__ __launch_bounds__(kWG) void force_kernel(ForceArgs a) {
+  using R = real_t<PREC>;
+  constexpr int REC = rec4<PREC>();
+  constexpr int kLoads = kTile * REC / kWG;
+  constexpr int kRedBytes = kWG * 9 * 8; // 7 sums + r2 + slot per lane
+  constexpr int kTileBytes = kTile * REC * 16;
+  constexpr int kLdsBytes = kRedBytes > kTileBytes ? kRedBytes : kTileBytes;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[kLdsBytes];
+  float4 *tile = reinterpret_cast<float4 *>(lds);
+
+  const int tid = threadIdx.x;
+  const int ipw = a.ipw;
+  const int log2L = 8 - a.log2ipw;
+  const int L = 1 << log2L;
+  const int il = tid & (ipw - 1);
+  const int sub = tid >> a.log2ipw;
+  const int i = blockIdx.x * ipw + il;
+  const bool valid = i < a.ni;
+
+  IState<PREC> st;
+  int slot;
+  R h2;
+  load_i<PREC>(st, a, i, valid, slot, h2);
+  const R eps2 = static_cast<R>(a.eps2);
+  Totals t = {{0, 0, 0}, {0, 0, 0}, 0};
+  Sums<R> ts; // tile sums
+  ts.zero();
+  R gbest = R(INFINITY), ebest = R(INFINITY);
+  int grp = -1, eslot = -1;
+  int *nb_cnt = a.nb_count + (valid ? i : 0);
+  int *nb_row = a.nb_slot + static_cast<size_t>(valid ? i : 0) * kNbMax;
+  const int K = kTile >> log2L; // records per lane in a full tile
+
+  const int ntiles = (a.nj + kTile - 1) / kTile;
+  const int per = (ntiles + gridDim.y - 1) / gridDim.y;
+  const int tb = blockIdx.y * per;
+  const int te = min(ntiles, tb + per);
+  const float4 *jp = static_cast<const float4 *>(a.jpred);
+
+  for (int tt = tb; tt < te; ++tt) {
+    const int jbase = tt * kTile;
+    const int cnt = min(kTile, a.nj - jbase);
+    __syncthreads();
+    {
+      const float4 *src = jp + static_cast<size_t>(jbase) * REC;
+      const int n4 = cnt * REC;
+#pragma unroll
+      for (int q = 0; q < kLoads; ++q) {
+        const int idx = q * kWG + tid;
+        if (idx < n4) tile[idx] = src[idx];
+      }
+    }
+    __syncthreads();
+    const bool self_here = slot >= jbase && slot < jbase + cnt;
+    if (cnt < kTile || K < kGroup || __any(self_here)) {
+      MaskedRun<PREC, NBL> run;
+      run.start();
+      for (int jj = sub; jj < cnt; jj += L)
+        run.step(st, ts, tile + jj * REC, jbase + jj, slot, eps2, h2, ebest, eslot, nb_cnt, nb_row);
+      run.finish(ts);
+    } else {
+      unsigned nbm = 0u;
+      for (int k0 = 0; k0 < K; k0 += kGroup) {
+        R m = R(INFINITY);
+        if constexpr (PREC == G6MI_PREC_FP64) {
+#pragma unroll
+          for (int u = 0; u < kGroup; ++u)
+            m = fmin(m, pair_core<PREC>(st, ts, tile + (sub + ((k0 + u) << log2L)) * REC, eps2));
+        } else {
+          Sums<R> gs; // group sums, set by the group's first pair
+          m = pair_core<PREC, true>(st, gs, tile + (sub + (k0 << log2L)) * REC, eps2);
+#pragma unroll
+          for (int u = 1; u < kGroup; ++u)
+            m = fmin(m, pair_core<PREC>(st, gs, tile + (sub + ((k0 + u) << log2L)) * REC, eps2));
+          ts.add(gs);
+        }
+        if (m < gbest) {
+          gbest = m;
+          grp = jbase + sub + (k0 << log2L);
+        }
+        if constexpr (NBL) nbm |= (m < h2 ? 1u : 0u) << (k0 / kGroup);
+      }
+      if constexpr (NBL) {
+        while (nbm) { // rare: append the neighbours of the flagged groups
+          const int g = __builtin_ctz(nbm);
+          nbm &= nbm - 1u;
+          for (int u = 0; u < kGroup; ++u) {
+            const int jj = sub + ((g * kGroup + u) << log2L);
+            if (r2_of<PREC>(st, tile + jj * REC) < h2) nb_append(a.nb_count, a.nb_slot, i, jbase + jj);
+          }
+        }
+      }
+    }
+    fold(ts, t);
+  }
+
+  // exact slot of the grouped-path nearest neighbour: re-examine its group
+  if (grp >= 0) {
+    for (int u = 0; u < kGroup; ++u) {
+      const int js = grp + (u << log2L); // within one full tile, so < nj
+      const R r = r2_of<PREC>(st, jp + static_cast<size_t>(js) * REC);
+      if (r < ebest || (r == ebest && js < eslot)) {
+        ebest = r;
+        eslot = js;
+      }
+    }
+  }
+
+  double bestd = static_cast<double>(ebest);
+  int bslot = eslot;
+  if (L > 1) {
+    __syncthreads();
+    double *red = reinterpret_cast<double *>(lds); // [9][kWG]
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      red[d * kWG + tid] = t.acc[d];
+      red[(3 + d) * kWG + tid] = t.jrk[d];
+    }
+    red[6 * kWG + tid] = t.pot;
+    red[7 * kWG + tid] = bestd;
+    reinterpret_cast<int *>(red + 8 * kWG)[tid] = bslot;
+    __syncthreads();
+    if (sub == 0) {
+      for (int q = 1; q < L; ++q) {
+        const int o = q * ipw + il;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          t.acc[d] += red[d * kWG + o];
+          t.jrk[d] += red[(3 + d) * kWG + o];
+        }
+        t.pot += red[6 * kWG + o];
+        const double r2o = red[7 * kWG + o];
+        const int so = reinterpret_cast<const int *>(red + 8 * kWG)[o];
+        if (so >= 0 && (r2o < bestd || (r2o == bestd && (bslot < 0 || so < bslot)))) {
+          bestd = r2o;
+          bslot = so;
+        }
+      }
+    }
+  }
+  if (sub == 0 && valid) {
+    const size_t ni = static_cast<size_t>(a.ni);
+    double *p = a.part + static_cast<size_t>(blockIdx.y) * 7 * ni + i;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      p[d * ni] = t.acc[d];
+      p[(3 + d) * ni] = t.jrk[d];
+    }
+    p[6 * ni] = t.pot;
+    a.nn_r2[blockIdx.y * ni + i] = bestd;
+    a.nn_slot[blockIdx.y * ni + i] = bslot;
+  }
+}
+
 // --------------------------------------------------------------- reduction
 
 // One thread per i-particle: float64 sum over the j-splits in split order,
 // lexicographic (r2, slot) minimum for the nearest neighbour, and the
 // neighbour list turned from slots into particle indices sorted ascending.
-// flags bit 0: a non-finite output; bit 1: a neighbour list overflowed.
+// status[kStatusFlags] bit 0: a non-finite output; bit 1: a neighbour list
+// overflowed.  Overflowed i-particles are queued in ovf_list for
+// nb_exact_kernel (status[kStatusOverflowCount] of them).
 __global__ __launch_bounds__(256) void reduce_kernel(
     int nsplit, int ni, const double *__restrict__ part,
     const double *__restrict__ nn_r2, const int *__restrict__ nn_slot,
     const int *__restrict__ jindex, const int *__restrict__ nb_count,
     int *__restrict__ nb_slot, int nbl, double *__restrict__ acc,
     double *__restrict__ jerk, double *__restrict__ pot, int *__restrict__ nnb,
-    double *__restrict__ r2nn, int *__restrict__ flags) {
+    double *__restrict__ r2nn, int *__restrict__ status, int *__restrict__ ovf_list) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= ni) return;
   const size_t n = static_cast<size_t>(ni);
@@ -677,9 +762,14 @@ __global__ __launch_bounds__(256) void reduce_kernel(
   int fl = finite ? 0 : 1;
   if (nbl) {
     const int cnt = nb_count[i];
-    const int k = cnt < kNbMax ? cnt : kNbMax;
-    if (cnt > kNbMax) fl |= 2;
     int *row = nb_slot + static_cast<size_t>(i) * kNbMax;
+    if (cnt > kNbMax) { // kept set decided later by nb_exact_kernel
+      fl |= 2;
+      ovf_list[atomicAdd(status + kStatusOverflowCount, 1)] = i;
+      if (fl) atomicOr(status + kStatusFlags, fl);
+      return;
+    }
+    const int k = cnt;
     for (int a = 0; a < k; ++a) row[a] = jindex[row[a]];
     for (int a = 1; a < k; ++a) { // insertion sort: lists are short
       const int key = row[a];
@@ -691,7 +781,73 @@ __global__ __launch_bounds__(256) void reduce_kernel(
       row[b + 1] = key;
     }
   }
-  if (fl) atomicOr(flags, fl);
+  if (fl) atomicOr(status + kStatusFlags, fl);
+}
+
+// --------------------------------------------- neighbour-list overflow
+
+// For every i-particle whose neighbour count exceeded kNbMax, rebuild its
+// list as the kNbMax smallest particle indices among its neighbours, in
+// ascending order (the oracle's convention).  One workgroup per queued
+// i-particle, grid-strided over the queue.  The neighbour test is the one of
+// the interaction kernels (same separation and r^2 arithmetic), repeated
+// over all nj slots: a binary search on the index threshold T counts the
+// neighbours with index below T (indices biased to unsigned order), then
+// the kNbMax of them below the final T are collected and rank-sorted.
+template <int PREC>
+__global__ __launch_bounds__(kWG) void nb_exact_kernel(ForceArgs a, const int *__restrict__ jindex,
+                                                        const int *__restrict__ status,
+                                                        const int *__restrict__ ovf_list) {
+  using R = real_t<PREC>;
+  constexpr int REC = rec4<PREC>();
+  __shared__ unsigned s_cnt;
+  __shared__ int s_keep[kNbMax];
+  const int tid = threadIdx.x;
+  const float4 *jp = static_cast<const float4 *>(a.jpred);
+  const int novf = status[kStatusOverflowCount];
+  for (int q = blockIdx.x; q < novf; q += gridDim.x) {
+    const int i = ovf_list[q];
+    IState<PREC> st;
+    int slot;
+    R h2;
+    load_i<PREC>(st, a, i, true, slot, h2);
+    auto below = [&](unsigned long long T, bool collect) -> unsigned {
+      __syncthreads();
+      if (tid == 0) s_cnt = 0u;
+      __syncthreads();
+      unsigned c = 0u;
+      for (int js = tid; js < a.nj; js += kWG) {
+        const unsigned key = static_cast<unsigned>(jindex[js]) ^ 0x80000000u;
+        if (js != slot && key < T && r2_of<PREC>(st, jp + static_cast<size_t>(js) * REC) < h2) {
+          if (collect) {
+            const unsigned p = atomicAdd(&s_cnt, 1u);
+            if (p < static_cast<unsigned>(kNbMax)) s_keep[p] = jindex[js];
+          } else {
+            ++c;
+          }
+        }
+      }
+      if (!collect && c) atomicAdd(&s_cnt, c);
+      __syncthreads();
+      return s_cnt;
+    };
+    // smallest T with at least kNbMax neighbours below it
+    unsigned long long lo = 0ull, hi = 1ull << 32;
+    while (hi - lo > 1ull) {
+      const unsigned long long mid = (lo + hi) >> 1;
+      if (below(mid, false) >= static_cast<unsigned>(kNbMax)) hi = mid;
+      else lo = mid;
+    }
+    const unsigned got = below(hi, true);
+    const int n = got < static_cast<unsigned>(kNbMax) ? static_cast<int>(got) : kNbMax;
+    int *row = a.nb_slot + static_cast<size_t>(i) * kNbMax;
+    if (tid < n) { // rank sort; equal values ranked by position
+      const int v = s_keep[tid];
+      int r = 0;
+      for (int u = 0; u < n; ++u) r += (s_keep[u] < v) | ((s_keep[u] == v) & (u < tid));
+      row[r] = v;
+    }
+  }
 }
 
 // ------------------------------------------------------------ j-memory I/O
@@ -741,22 +897,23 @@ __global__ __launch_bounds__(256) void load_kernel(int nj, const double *__restr
 static inline unsigned blocks_for(long n) { return static_cast<unsigned>((n + 255) / 256); }
 
 hipError_t launch_predict(int prec, int nj, double ti, const JMem &jm, void *out,
-                          int *nb_count, int ni, hipStream_t s) {
-  const long n = nj > ni ? nj : ni;
+                          int *nb_count, int ni, int *status, hipStream_t s) {
+  long n = nj > ni ? nj : ni;
+  if (n < kStatusWords) n = kStatusWords;
   if (n <= 0) return hipSuccess;
   const dim3 grid(blocks_for(n)), block(256);
   switch (prec) {
   case G6MI_PREC_FP32:
     hipLaunchKernelGGL(predict_kernel<G6MI_PREC_FP32>, grid, block, 0, s, nj, ti, jm.t, jm.m,
-                       jm.x, jm.v, jm.a2, jm.j6, jm.cap, out, nb_count, ni);
+                       jm.x, jm.v, jm.a2, jm.j6, jm.cap, out, nb_count, ni, status);
     break;
   case G6MI_PREC_DS:
     hipLaunchKernelGGL(predict_kernel<G6MI_PREC_DS>, grid, block, 0, s, nj, ti, jm.t, jm.m,
-                       jm.x, jm.v, jm.a2, jm.j6, jm.cap, out, nb_count, ni);
+                       jm.x, jm.v, jm.a2, jm.j6, jm.cap, out, nb_count, ni, status);
     break;
   default:
     hipLaunchKernelGGL(predict_kernel<G6MI_PREC_FP64>, grid, block, 0, s, nj, ti, jm.t, jm.m,
-                       jm.x, jm.v, jm.a2, jm.j6, jm.cap, out, nb_count, ni);
+                       jm.x, jm.v, jm.a2, jm.j6, jm.cap, out, nb_count, ni, status);
   }
   return hipGetLastError();
 }
@@ -788,11 +945,30 @@ hipError_t launch_force(int prec, bool nbl, const ForceArgs &a, int nsplit, hipS
 hipError_t launch_reduce(int nsplit, int ni, const double *part, const double *nn_r2,
                          const int *nn_slot, const int *jindex, int *nb_count, int *nb_slot,
                          bool nbl, double *acc, double *jerk, double *pot, int *nnb,
-                         double *r2nn, int *flags, hipStream_t s) {
+                         double *r2nn, int *status, int *ovf_list, hipStream_t s) {
   if (ni <= 0) return hipSuccess;
   hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(ni)), dim3(256), 0, s, nsplit, ni, part,
                      nn_r2, nn_slot, jindex, nb_count, nb_slot, nbl ? 1 : 0, acc, jerk, pot,
-                     nnb, r2nn, flags);
+                     nnb, r2nn, status, ovf_list);
+  return hipGetLastError();
+}
+
+template <int PREC>
+static void launch_exact_prec(const ForceArgs &a, const int *jindex, const int *status,
+                              const int *ovf_list, int ngroups, hipStream_t s) {
+  hipLaunchKernelGGL(nb_exact_kernel<PREC>, dim3(ngroups), dim3(kWG), 0, s, a, jindex,
+                     status, ovf_list);
+}
+
+hipError_t launch_nb_exact(int prec, const ForceArgs &a, const int *jindex, const int *status,
+                           const int *ovf_list, int novf, hipStream_t s) {
+  if (novf <= 0) return hipSuccess;
+  const int ngroups = novf < 1024 ? novf : 1024;
+  switch (prec) {
+  case G6MI_PREC_FP32: launch_exact_prec<G6MI_PREC_FP32>(a, jindex, status, ovf_list, ngroups, s); break;
+  case G6MI_PREC_DS: launch_exact_prec<G6MI_PREC_DS>(a, jindex, status, ovf_list, ngroups, s); break;
+  default: launch_exact_prec<G6MI_PREC_FP64>(a, jindex, status, ovf_list, ngroups, s);
+  }
   return hipGetLastError();
 }
 

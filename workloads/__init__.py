@@ -18,6 +18,8 @@ from .generators import (  # noqa: F401
     config_c2,
     config_c3,
     config_c5,
+    config_c4,
+    ClusterBatch,
     active_set,
     random_cluster,
     input_digest,

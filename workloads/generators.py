@@ -275,6 +275,64 @@ def random_cluster(n: int, seed: int, ti: float = 2.0 ** -6,
         name=f"random_cluster_N{n}_seed{seed}", ti=ti, seed=seed))
 
 
+@dataclass
+class ClusterBatch:
+    """Independent clusters concatenated in one j-memory: cluster c owns
+    slots joff[c] .. joff[c+1]-1; its active i-particles are the slots in
+    active[ioff[c] .. ioff[c+1]-1]; ti[c] and eps2[c] are its own prediction
+    time and softening."""
+
+    jm: JMemory
+    joff: np.ndarray
+    ioff: np.ndarray
+    active: np.ndarray
+    ti: np.ndarray
+    eps2: np.ndarray
+    h2: np.ndarray
+
+    @property
+    def nclusters(self) -> int:
+        return int(self.joff.shape[0] - 1)
+
+
+def config_c4(seed: int = 4, nclusters: int = 256, n_lo: int = 256, n_hi: int = 8192) -> ClusterBatch:
+    """Batched workload: independent Plummer clusters with N log-uniform in
+    [n_lo, n_hi], Salpeter masses (each cluster's total mass 1), centres
+    offset uniformly in [-100, 100]^3, individual block times (power-of-two
+    steps below each cluster's own time) and their own active blocks (2^k
+    particles, k uniform in 0 .. log2 N).  Softening 1e-4 for every cluster,
+    neighbour radius 0.01."""
+    rng = _rng(seed)
+    sizes = np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), nclusters)).astype(np.int64)
+    joff = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    ntot = int(joff[-1])
+    x = np.empty((ntot, 3)); v = np.empty((ntot, 3)); m = np.empty(ntot)
+    t = np.empty(ntot); a2 = np.empty((ntot, 3)); j6 = np.empty((ntot, 3))
+    ti = np.empty(nclusters)
+    active = []
+    ioff = [0]
+    for c in range(nclusters):
+        n = int(sizes[c]); lo, hi = int(joff[c]), int(joff[c + 1])
+        mc = salpeter_masses(n, rng)
+        xc, vc = plummer(n, rng, masses=mc)
+        x[lo:hi] = xc + rng.uniform(-100.0, 100.0, 3)
+        v[lo:hi] = vc
+        m[lo:hi] = mc
+        ti[c] = rng.integers(1, 64) * 2.0 ** -8
+        dt = 2.0 ** -rng.integers(6, 12, n)
+        t[lo:hi] = ti[c] - dt * rng.integers(0, 2, n)
+        ac, jc = synthetic_derivatives(n, rng)
+        a2[lo:hi], j6[lo:hi] = ac, jc
+        k = int(rng.integers(0, int(np.log2(n)) + 1))
+        act = np.sort(rng.permutation(n)[: 2 ** k]) + lo
+        active.append(act)
+        ioff.append(ioff[-1] + len(act))
+    jm = make_jmemory(x, v, m, t=t, a2=a2, j6=j6, meta=dict(name=f"clusters{nclusters}_N{n_lo}-{n_hi}", seed=seed))
+    return ClusterBatch(jm=jm, joff=joff, ioff=np.array(ioff, dtype=np.int64),
+                        active=np.concatenate(active).astype(np.int32), ti=ti,
+                        eps2=np.full(nclusters, 1e-8), h2=np.full(nclusters, 1e-4))
+
+
 def input_digest(*arrays) -> str:
     """sha256 over the raw bytes of the given arrays (logged with results)."""
     h = hashlib.sha256()
