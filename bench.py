@@ -33,8 +33,8 @@ FLOP_PER_PAIR = 60          # Sec. 3.1 convention, used for every variant
 PEAK_FP32_TFLOPS = 157.3    # MI355X vector FP32 (dense)
 PEAK_FP64_TFLOPS = 78.6     # MI355X vector FP64
 METRIC = "pair interactions/s & Gflop/s (60 flop/pair) at N=2^20, DS vs FP64 at stated err"
-KERNEL_SOURCES = ("paper_0902_4463_amd/csrc/g6mi_kernels.hip", "paper_0902_4463_amd/csrc/g6mi_internal.h",
-                  "paper_0902_4463_amd/csrc/g6mi_api.cpp")
+KERNEL_SOURCES = ("paper_0902_4463_amd/csrc/g6mi_kernels.hip", "paper_0902_4463_amd/csrc/g6mi_device.h",
+                  "paper_0902_4463_amd/csrc/g6mi_internal.h")
 TRAFFIC_PROFILE = "profiles/force_wide_ds_plummer_N1048576_traffic.md"
 
 
@@ -80,7 +80,126 @@ def parse():
     ap.add_argument("--shape", default=None, help="i_per_group,j_splits override")
     ap.add_argument("--sweep", default=None,
                     help="comma-separated k: also time active blocks of 2^k against all N (DS and FP64)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-cluster workload")
+    ap.add_argument("--batched-steps", type=int, default=20)
+    ap.add_argument("--tune-cache", default=None, help="tuning cache file of the batched launch")
     return ap.parse_args()
+
+
+def batched_bench(args, g6, torch, dev):
+    """256 independent Plummer clusters (N log-uniform in [256, 8192],
+    Salpeter masses, own centres, times and active blocks of 2^k): one
+    batched launch (plan + persistent kernel, replayed as a HIP graph) per
+    step, against the same work as one single-system call per cluster."""
+    import workloads
+    cb = workloads.config_c4()
+    jm = cb.jm
+    ncl = cb.nclusters
+    nj = np.diff(cb.joff)
+    ni_c = np.diff(cb.ioff)
+    n_i = len(cb.active)
+    pairs = float(np.sum(ni_c.astype(np.float64) * nj))
+    log(f"[bench] batched: {ncl} clusters, {jm.n} j, {n_i} i, {pairs:.3e} pairs")
+    hid = 1
+    g6.check(hid, g6.g6_open(hid))
+    g6.check(hid, g6.g6mi_set_precision(hid, "ds"))
+    t = {k: torch.tensor(getattr(jm, k), device=dev) for k in ("t", "m", "index", "x", "v", "a2", "j6")}
+    g6.check(hid, g6.g6mi_set_j_particles_device(hid, jm.n, t["t"], t["m"], t["index"], t["x"], t["v"], t["a2"],
+                                                t["j6"]))
+    act = torch.tensor(cb.active.astype(np.int64), device=dev)
+    islot = act.to(torch.int32)
+    xi = t["x"][act].contiguous()
+    vi = t["v"][act].contiguous()
+    h2 = torch.tensor(np.repeat(cb.h2, ni_c), device=dev)
+    out = [torch.empty((n_i, 3), dtype=torch.float64, device=dev), torch.empty((n_i, 3), dtype=torch.float64, device=dev),
+           torch.empty(n_i, dtype=torch.float64, device=dev), torch.empty(n_i, dtype=torch.int32, device=dev),
+           torch.empty(n_i, dtype=torch.float64, device=dev)]
+    cl = g6.clusters(cb.joff[:-1], nj, cb.ioff[:-1], ni_c, cb.ti, cb.eps2)
+    stream = torch.cuda.Stream()
+    args_dev = (islot, xi, vi, h2, *out)
+    with torch.cuda.stream(stream):
+        rc, tuning = g6.g6mi_batch_autotune(hid, cl, n_i, *args_dev, stream=stream, cache_path=args.tune_cache)
+        g6.check(hid, rc)
+    torch.cuda.synchronize()
+    log(f"[bench] batched tuning {tuning}")
+
+    def timed(fn, steps):
+        with torch.cuda.stream(stream):
+            for _ in range(2):
+                fn()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    def batch_step():
+        g6.check(hid, g6.g6mi_batch_calc(hid, cl, n_i, *args_dev, stream=stream))
+
+    steps = args.batched_steps
+    g6.check(hid, g6.g6mi_batch_use_graph(hid, 1))
+    ms_graph = timed(batch_step, steps)
+    g6.check(hid, g6.g6mi_batch_use_graph(hid, 0))
+    ms_direct = timed(batch_step, steps)
+    g6.check(hid, g6.g6mi_enable_timing(hid, 1))
+    with torch.cuda.stream(stream):
+        for _ in range(steps):
+            batch_step()
+    torch.cuda.synchronize()
+    tot = g6.g6mi_timing_totals(hid)
+    g6.check(hid, g6.g6mi_enable_timing(hid, 0))
+    force_ms = tot["force_ms"] / max(1, tot["count"])
+    plan_ms = tot["predict_ms"] / max(1, tot["count"])
+    res_batch = [o.cpu().numpy().copy() for o in out]
+
+    # the same work as one call per cluster: a handle per cluster holding its
+    # j-slots, each call predicting, interacting and reducing on its own
+    ids = list(range(2, 2 + ncl))
+    loc_slot = []
+    for c, h in enumerate(ids):
+        lo, hi = int(cb.joff[c]), int(cb.joff[c + 1])
+        g6.check(h, g6.g6_open(h))
+        g6.check(h, g6.g6mi_set_precision(h, "ds"))
+        g6.check(h, g6.g6mi_set_j_particles_device(h, hi - lo, t["t"][lo:hi], t["m"][lo:hi], t["index"][lo:hi],
+                                                  t["x"][lo:hi], t["v"][lo:hi], t["a2"][lo:hi], t["j6"][lo:hi]))
+        g6.g6_set_ti(h, float(cb.ti[c]))
+        loc_slot.append((islot[int(cb.ioff[c]):int(cb.ioff[c + 1])] - lo).contiguous())
+
+    def separate_step():
+        for c, h in enumerate(ids):
+            a0, a1 = int(cb.ioff[c]), int(cb.ioff[c + 1])
+            if a1 == a0:
+                continue
+            g6.check(h, g6.g6mi_calc_device(h, int(nj[c]), a1 - a0, loc_slot[c], xi[a0:a1], vi[a0:a1],
+                                            float(cb.eps2[c]), h2[a0:a1], out[0][a0:a1], out[1][a0:a1],
+                                            out[2][a0:a1], out[3][a0:a1], out[4][a0:a1], stream=stream))
+
+    w0 = time.perf_counter()
+    ms_sep = timed(separate_step, max(3, steps // 4))
+    log(f"[bench] batched: graph {ms_graph:.3f} ms, direct {ms_direct:.3f} ms, separate calls {ms_sep:.3f} ms "
+        f"({time.perf_counter() - w0:.1f} s)")
+    res_sep = [o.cpu().numpy() for o in out]
+    # the two paths agree (rounding of the float64 split sums aside)
+    da = np.linalg.norm(res_batch[0] - res_sep[0], axis=1) / np.maximum(np.linalg.norm(res_sep[0], axis=1), 1e-300)
+    for h in ids:
+        g6.g6_close(h)
+    g6.g6_close(hid)
+    force_tf = FLOP_PER_PAIR * pairs / (force_ms * 1e-3) / 1e12
+    return dict(
+        workload=f"{ncl} Plummer clusters, N log-uniform 256..8192 ({jm.n} j, {n_i} active i), Salpeter, DS",
+        pairs=pairs, steps=steps, tuning=tuning,
+        graph=dict(ms_per_step=round(ms_graph, 4), pairs_per_s=pairs / (ms_graph * 1e-3)),
+        direct=dict(ms_per_step=round(ms_direct, 4), pairs_per_s=pairs / (ms_direct * 1e-3),
+                    plan_ms=round(plan_ms, 4), force_ms=round(force_ms, 4)),
+        separate_calls=dict(ms_per_step=round(ms_sep, 4), pairs_per_s=pairs / (ms_sep * 1e-3), calls=ncl),
+        speedup_vs_separate=round(ms_sep / ms_graph, 2),
+        roofline=dict(bound="alu", kernel="batch_kernel<ds>", achieved=round(force_tf, 3),
+                      peak=PEAK_FP32_TFLOPS, unit="TFLOP/s", frac=round(force_tf / PEAK_FP32_TFLOPS, 4)),
+        max_rel_acc_diff_vs_separate=float(da.max()))
 
 
 def main():
@@ -274,6 +393,10 @@ def main():
             log(f"[bench] sweep k={k}: ds {entry['ds']['ms_per_step']} ms, fp64 {entry['fp64']['ms_per_step']} ms")
             sweep.append(entry)
 
+    batched = None
+    if not args.no_batched:
+        batched = batched_bench(args, g6, torch, dev)
+
     line = dict(
         metric=METRIC, value=value, unit="pairs/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
         ms_per_step=round(main_run["ms_per_step"], 4), higher_is_better=True, scaling="weak",
@@ -285,7 +408,7 @@ def main():
                     parallelism="single-gpu"),
         kernel_ms=dict(predict=round(main_run["predict_ms"], 4), force=round(main_run["force_ms"], 4),
                        reduce=round(main_run["reduce_ms"], 4)),
-        roofline=roofline, variants=variants, accuracy=accuracy, cpu_baseline=cpu, sweep=sweep,
+        roofline=roofline, variants=variants, accuracy=accuracy, cpu_baseline=cpu, sweep=sweep, batched=batched,
         device=dict(compute_units=info["compute_units"], clock_mhz=info["clock_mhz"],
                     name=torch.cuda.get_device_name(0)),
     )

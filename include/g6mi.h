@@ -51,6 +51,7 @@ extern "C" {
 
 /* ------------------------------------------------------------ constants */
 
+
 /* Maximum neighbours stored per i-particle (Sec. 4: fixed at build time,
  * default 256). */
 #define G6MI_NB_MAX 256
@@ -59,7 +60,7 @@ extern "C" {
 #define G6MI_NPIPES_DEFAULT 256
 #define G6MI_NI_MAX (1 << 24)
 #define G6MI_NJ_MAX (1 << 26)
-#define G6MI_MAX_HANDLES 16
+#define G6MI_MAX_HANDLES 1024
 
 /* Precision variants of the pair interaction (Sec. 2.2-2.3). */
 #define G6MI_PREC_FP32 0 /* float32 positions and arithmetic                */
@@ -75,6 +76,21 @@ extern "C" {
 #define G6MI_ESTATE    (-2) /* handle not open, or call out of sequence      */
 #define G6MI_EDEVICE   (-3) /* no usable GPU, or a HIP runtime error         */
 #define G6MI_ENOMEM    (-4) /* GPU or pinned host allocation failed          */
+
+/* One cluster of a batched calculation (g6mi_batch_calc): an independent
+ * system whose j-particles are the slots joff .. joff+nj-1 of the handle's
+ * j-memory, predicted to the cluster's own time ti, and whose i-particles
+ * are the rows ioff .. ioff+ni-1 of the batch's i-arrays.  Each i-particle
+ * interacts only with its own cluster's j-slots, softened by the cluster's
+ * eps2.  32 bytes, no padding. */
+typedef struct g6mi_cluster {
+  int joff;    /* first j-slot                                   */
+  int nj;      /* number of j-slots (>= 0)                       */
+  int ioff;    /* first row in the i-arrays and output arrays    */
+  int ni;      /* number of i-particles (>= 0)                   */
+  double ti;   /* prediction time of the cluster's j-particles   */
+  double eps2; /* softening squared (finite, >= 0)               */
+} g6mi_cluster;
 
 /* ------------------------------------------------- GRAPE-6 calling sequence */
 
@@ -264,6 +280,109 @@ int g6mi_calc_device(int id, int nj, int ni, const int *d_islot,
 /* Device properties used by the launch heuristics: compute units and peak
  * engine clock in MHz.  Returns 0 or a negative code. */
 int g6mi_device_info(int id, int info[2]);
+
+/* Status flags of the last calculation on handle id (waits for it): bit 0
+ * a non-finite output, bit 1 a neighbour list overflowed G6MI_NB_MAX, bit 2
+ * (batched calls) a cluster descriptor was invalid and its cluster skipped.
+ * Returns 0, G6MI_ESTATE (no calculation) or a negative code. */
+int g6mi_last_status(int id, int *flags);
+
+/* --------------------------------------------- batched multi-cluster calls
+ *
+ * Many independent clusters (GRAPE-6 "cluster ids") evaluated in one
+ * launch: the j-particles of every cluster live in the one j-memory of
+ * handle id (set as usual with g6_set_j_particle / g6mi_set_j_particles /
+ * g6mi_set_j_particles_device), each cluster at its own slots; the
+ * i-particles of all clusters are the rows 0 .. ni_total-1 of one set of
+ * device arrays, in the layout of g6mi_calc_device (d_islot[r] is the
+ * j-slot holding row r's own particle, or -1; d_xi, d_vi [ni_total][3];
+ * d_h2 [ni_total]), and so are the outputs (d_acc, d_jerk [ni_total][3],
+ * d_pot, d_nnb, d_r2nn [ni_total]; d_nnb and d_r2nn may be NULL).  Row r of
+ * cluster c gets, exactly as a separate g6mi_calc_device on that cluster
+ * alone would give (up to the order of float64 additions), the forces of
+ * c's j-slots predicted to c's ti and softened by c's eps2 (Sec. 2.2-2.3),
+ * its nearest neighbour among them, and its neighbour list (read afterwards
+ * with g6_read_neighbour_list / g6_get_neighbour_list, ipipe = r).
+ *
+ * One plan kernel and one persistent kernel: work items (cluster, i-block,
+ * j-split) are taken from a queue, each predicts its j-tiles in on-chip
+ * memory and the last split of each i-block writes the results.  All work
+ * is enqueued on `stream` (NULL: the handle's stream) without host
+ * synchronisation.  The caller keeps every device buffer valid until the
+ * work has completed (and the i-arrays until g6_read_neighbour_list).
+ *
+ * g6mi_batch_calc takes the ncl descriptors in host memory; they are checked
+ * (ranges inside the slots set from slot 0 and inside 0 .. ni_total-1,
+ * finite ti and eps2 >= 0, no two clusters sharing an i-row) and copied.
+ * Returns 0, G6MI_EINVAL, G6MI_ESTATE, G6MI_EDEVICE or G6MI_ENOMEM.
+ *
+ * g6mi_batch_calc_device takes them in device memory (d_cl, read when the
+ * work runs, so it may be filled by earlier work on the stream); an invalid
+ * descriptor is not an error at the call: its cluster is skipped and bit 2
+ * of g6mi_last_status is set.  Clusters must not share i-rows. */
+int g6mi_batch_calc(int id, int ncl, const g6mi_cluster *cl, int ni_total,
+                    const int *d_islot, const double *d_xi,
+                    const double *d_vi, const double *d_h2, double *d_acc,
+                    double *d_jerk, double *d_pot, int *d_nnb,
+                    double *d_r2nn, void *stream);
+int g6mi_batch_calc_device(int id, int ncl, const g6mi_cluster *d_cl,
+                           int ni_total, const int *d_islot,
+                           const double *d_xi, const double *d_vi,
+                           const double *d_h2, double *d_acc, double *d_jerk,
+                           double *d_pot, int *d_nnb, double *d_r2nn,
+                           void *stream);
+
+/* Graph mode (1) or direct launches (0, default) for batched calls.  In
+ * graph mode the plan and persistent kernels are captured once into a HIP
+ * graph and the graph is replayed by later batched calls whose arguments
+ * (pointers, ncl, ni_total, variant, tuning, stream) are all unchanged;
+ * descriptor and particle contents may change between replays.  Any change
+ * captures a new graph.  Returns 0 or a negative code. */
+int g6mi_batch_use_graph(int id, int on);
+
+/* Launch policy of batched calls.
+ *   item_work  work per item, in units of one j-tile of 256 records
+ *              against 512 i-particles (1 .. 1024; default 2)
+ *   wide_min   clusters with at least this many i-particles use two
+ *              i-particles per lane (default 512)
+ *   wg_per_cu  persistent workgroups per compute unit (0: the kernel's
+ *              occupancy, 3, or 2 for float64; 1 .. 8)
+ *   max_split  most j-splits per cluster (1 .. 4096; default 64; lowered
+ *              so that the partial sums stay within 4 GiB) */
+typedef struct g6mi_batch_tuning {
+  int item_work;
+  int wide_min;
+  int wg_per_cu;
+  int max_split;
+} g6mi_batch_tuning;
+
+/* Set (t = NULL: the defaults) or read the launch policy.  Returns 0 or a
+ * negative code. */
+int g6mi_batch_set_tuning(int id, const g6mi_batch_tuning *t);
+int g6mi_batch_get_tuning(int id, g6mi_batch_tuning *t);
+
+/* Choose the launch policy for batches like the given one.  The key is the
+ * device, the precision variant, neighbour lists on/off, ncl and the log2
+ * size classes of the batch's pairs, i-particles and j-slots.  When the
+ * key is in this process's table or in the text file cache_path (or the
+ * file named by the environment variable G6MI_TUNE_CACHE when cache_path is
+ * NULL; lines "g6mi-batch-tune-v1 key item_work wide_min wg_per_cu
+ * max_split ms", the last line for a key wins) that policy is applied.
+ * Otherwise every combination of item_work 1, 2, 4, 8, 16, wide_min 257,
+ * 512, 1024 and wg_per_cu 1 .. occupancy is timed on this batch (one
+ * untimed and `reps` timed runs each, reps <= 0 meaning 3; the output
+ * arrays are overwritten), the fastest is applied and appended to the file.
+ * The chosen policy is written to *best when best is not NULL.  Returns 0,
+ * 1 if the cache file could not be written (the policy is still applied),
+ * or a negative code. */
+int g6mi_batch_autotune(int id, int ncl, const g6mi_cluster *cl,
+                        int ni_total, const int *d_islot, const double *d_xi,
+                        const double *d_vi, const double *d_h2,
+                        double *d_acc, double *d_jerk, double *d_pot,
+                        int *d_nnb, double *d_r2nn, void *stream,
+                        const char *cache_path, int reps,
+                        g6mi_batch_tuning *best);
+
 
 /* ------------------------------------------------------ Fortran aliases */
 int g6_open_(const int *id);

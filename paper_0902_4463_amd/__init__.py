@@ -28,10 +28,25 @@ NB_MAX = 256
 NPIPES_DEFAULT = 256
 NI_MAX = 1 << 24
 NJ_MAX = 1 << 26
-MAX_HANDLES = 16
+MAX_HANDLES = 1024
 PREC_FP32, PREC_DS, PREC_FP64 = 0, 1, 2
 PRECISIONS = {"fp32": PREC_FP32, "ds": PREC_DS, "fp64": PREC_FP64}
 OK, WARN, EINVAL, ESTATE, EDEVICE, ENOMEM = 0, 1, -1, -2, -3, -4
+FLAG_NONFINITE, FLAG_NB_OVERFLOW, FLAG_BAD_CLUSTER = 1, 2, 4
+
+# struct g6mi_cluster (32 bytes, no padding)
+CLUSTER_DTYPE = np.dtype([("joff", "<i4"), ("nj", "<i4"), ("ioff", "<i4"), ("ni", "<i4"),
+                          ("ti", "<f8"), ("eps2", "<f8")])
+assert CLUSTER_DTYPE.itemsize == 32
+
+
+class BatchTuning(ctypes.Structure):
+    """struct g6mi_batch_tuning."""
+    _fields_ = [("item_work", ctypes.c_int), ("wide_min", ctypes.c_int), ("wg_per_cu", ctypes.c_int),
+                ("max_split", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 _D = ctypes.POINTER(ctypes.c_double)
 _I = ctypes.POINTER(ctypes.c_int)
@@ -66,6 +81,14 @@ _SIGS = {
     "g6mi_set_j_particles_device": (_i, [_i, _i, _V, _V, _V, _V, _V, _V, _V, _V]),
     "g6mi_calc_device": (_i, [_i, _i, _i, _V, _V, _V, _d, _V, _V, _V, _V, _V, _V, _V]),
     "g6mi_device_info": (_i, [_i, _I]),
+    "g6mi_last_status": (_i, [_i, _I]),
+    "g6mi_batch_calc": (_i, [_i, _i, _V, _i, _V, _V, _V, _V, _V, _V, _V, _V, _V, _V]),
+    "g6mi_batch_calc_device": (_i, [_i, _i, _V, _i, _V, _V, _V, _V, _V, _V, _V, _V, _V, _V]),
+    "g6mi_batch_use_graph": (_i, [_i, _i]),
+    "g6mi_batch_set_tuning": (_i, [_i, ctypes.POINTER(BatchTuning)]),
+    "g6mi_batch_get_tuning": (_i, [_i, ctypes.POINTER(BatchTuning)]),
+    "g6mi_batch_autotune": (_i, [_i, _i, _V, _i, _V, _V, _V, _V, _V, _V, _V, _V, _V, _V, ctypes.c_char_p, _i,
+                                 ctypes.POINTER(BatchTuning)]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -294,6 +317,76 @@ def g6mi_device_info(id):
     out = np.zeros(2, dtype=np.int32)
     check(id, _L().g6mi_device_info(id, _pi(out)))
     return dict(compute_units=int(out[0]), clock_mhz=int(out[1]))
+
+
+def g6mi_last_status(id) -> int:
+    """Status flags of the last calculation (FLAG_* bits)."""
+    out = np.zeros(1, dtype=np.int32)
+    check(id, _L().g6mi_last_status(id, _pi(out)))
+    return int(out[0])
+
+
+# ------------------------------------------------------------ batched calls
+
+def clusters(joff, nj, ioff, ni, ti, eps2) -> np.ndarray:
+    """Cluster descriptors (struct g6mi_cluster) from per-cluster sequences."""
+    n = len(joff)
+    out = np.zeros(n, dtype=CLUSTER_DTYPE)
+    out["joff"], out["nj"], out["ioff"], out["ni"] = joff, nj, ioff, ni
+    out["ti"], out["eps2"] = ti, eps2
+    return out
+
+
+def _cl_host(cl):
+    cl = np.ascontiguousarray(cl, dtype=CLUSTER_DTYPE)
+    return cl, cl.ctypes.data
+
+
+def g6mi_batch_calc(id, cl, ni_total, islot, xi, vi, h2, acc, jerk, pot, nnb=None, r2nn=None,
+                    stream=None) -> int:
+    """cl: host descriptors (CLUSTER_DTYPE array); the rest device buffers."""
+    cl, addr = _cl_host(cl)
+    return _L().g6mi_batch_calc(id, len(cl), addr, int(ni_total), _ptr(islot), _ptr(xi), _ptr(vi), _ptr(h2),
+                                _ptr(acc), _ptr(jerk), _ptr(pot), _ptr(nnb), _ptr(r2nn), _stream(stream))
+
+
+def g6mi_batch_calc_device(id, ncl, d_cl, ni_total, islot, xi, vi, h2, acc, jerk, pot, nnb=None, r2nn=None,
+                           stream=None) -> int:
+    """d_cl: device buffer holding ncl descriptors (32 bytes each)."""
+    return _L().g6mi_batch_calc_device(id, int(ncl), _ptr(d_cl), int(ni_total), _ptr(islot), _ptr(xi),
+                                       _ptr(vi), _ptr(h2), _ptr(acc), _ptr(jerk), _ptr(pot), _ptr(nnb),
+                                       _ptr(r2nn), _stream(stream))
+
+
+def g6mi_batch_use_graph(id, on) -> int:
+    return _L().g6mi_batch_use_graph(id, int(bool(on)))
+
+
+def g6mi_batch_set_tuning(id, tuning=None) -> int:
+    """tuning: dict with item_work, wide_min, wg_per_cu, max_split, or None
+    for the defaults."""
+    if tuning is None:
+        return _L().g6mi_batch_set_tuning(id, None)
+    t = BatchTuning(**{k: int(v) for k, v in tuning.items()})
+    return _L().g6mi_batch_set_tuning(id, ctypes.byref(t))
+
+
+def g6mi_batch_get_tuning(id) -> dict:
+    t = BatchTuning()
+    check(id, _L().g6mi_batch_get_tuning(id, ctypes.byref(t)))
+    return t.as_dict()
+
+
+def g6mi_batch_autotune(id, cl, ni_total, islot, xi, vi, h2, acc, jerk, pot, nnb=None, r2nn=None,
+                        stream=None, cache_path=None, reps=3):
+    """Returns (rc, chosen tuning as a dict)."""
+    cl, addr = _cl_host(cl)
+    t = BatchTuning()
+    path = None if cache_path is None else os.fsencode(cache_path)
+    rc = _L().g6mi_batch_autotune(id, len(cl), addr, int(ni_total), _ptr(islot), _ptr(xi), _ptr(vi),
+                                  _ptr(h2), _ptr(acc), _ptr(jerk), _ptr(pot), _ptr(nnb), _ptr(r2nn),
+                                  _stream(stream), path, int(reps), ctypes.byref(t))
+    return rc, t.as_dict()
 
 
 # --------------------------------------------------- convenience wrappers

@@ -17,7 +17,9 @@
 
 #include <algorithm>
 #include <array>
+#include <climits>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -81,6 +83,7 @@ struct Handle {
   int device = 0;
   hipStream_t stream = nullptr;
   int ncu = 0, clock_mhz = 0;
+  std::string arch;
   int prec = G6MI_PREC_DS;
   bool nbl = true;
   int user_ipw = 0, user_nsplit = 0;
@@ -133,6 +136,20 @@ struct Handle {
   bool timing = false;
   int n_timed = 0;
   std::vector<std::array<hipEvent_t, 4>> evs;
+
+  // batched calculations
+  BatchTune btune;
+  int b_wg_per_cu = 0; // 0: as many as the kernel's occupancy allows
+  DevBuf d_cl, d_plan, d_items, d_bwork, d_ibcnt;
+  PinBuf h_cl;
+  hipEvent_t cl_ev = nullptr;
+  bool cl_busy = false;
+  bool use_graph = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<uint64_t> gkey;
+  bool c_batch = false;    // the last calculation was a batch
+  BatchArgs c_bargs;
 };
 
 constexpr int kTimingRing = 4096;
@@ -316,7 +333,7 @@ int enqueue_calc(Handle &h, int nj, int ni, const int *d_islot, const double *d_
   HIPCHK(&h, ensure(h.d_nbcount, n * sizeof(int)));
   HIPCHK(&h, ensure(h.d_nblist, n * kNbMax * sizeof(int)));
   HIPCHK(&h, ensure(h.d_flags, 64));
-  HIPCHK(&h, ensure(h.d_ovf, n * sizeof(int)));
+  HIPCHK(&h, ensure(h.d_ovf, 2 * n * sizeof(int)));
   int *status = static_cast<int *>(h.d_flags.p); // zeroed by the predictor launch
 
   h.shape[0] = ipw;
@@ -369,6 +386,7 @@ int enqueue_calc(Handle &h, int nj, int ni, const int *d_islot, const double *d_
   h.c_prec = h.prec;
   h.c_nbl = h.nbl;
   h.c_have = true;
+  h.c_batch = false;
   h.nb_read = false;
   h.nb_exact_done = false;
   return 0;
@@ -496,6 +514,230 @@ int lasthalf_impl(int id, int nj, int ni, const int *index, double eps2, double 
   return (ni > 0 && (flags & 1)) ? G6MI_WARN : G6MI_OK;
 }
 
+// ------------------------------------------------------------ batched path
+
+// Partial sums of a batch: at most this many bytes (7 sums, r^2 and slot per
+// i-particle and j-split); the j-split cap is lowered to fit.
+constexpr size_t kBatchPartialBudget = size_t(4) << 30;
+constexpr size_t kPartialEntryBytes = 7 * sizeof(double) + sizeof(double) + sizeof(int);
+constexpr int kBatchMaxClusters = 1 << 20;
+
+int batch_waves(int prec) { return prec == G6MI_PREC_FP64 ? 2 : 3; }
+
+int batch_grid(const Handle &h, int prec) {
+  const int w = h.b_wg_per_cu > 0 ? h.b_wg_per_cu : batch_waves(prec);
+  return std::max(1, h.ncu) * w;
+}
+
+void destroy_graph(Handle &h) {
+  if (h.gexec) (void)hipGraphExecDestroy(h.gexec);
+  if (h.graph) (void)hipGraphDestroy(h.graph);
+  h.gexec = nullptr;
+  h.graph = nullptr;
+  h.gkey.clear();
+}
+
+std::vector<uint64_t> graph_key(const Handle &h, const BatchArgs &b, int grid, hipStream_t s) {
+  auto u = [](const void *p) { return static_cast<uint64_t>(reinterpret_cast<uintptr_t>(p)); };
+  return {u(b.cl), u(b.plan), u(b.item_cl), u(b.work), static_cast<uint64_t>(b.ncl),
+          static_cast<uint64_t>(b.nj_set), static_cast<uint64_t>(b.ni_total),
+          static_cast<uint64_t>(b.item_cap), static_cast<uint64_t>(b.tune.item_work),
+          static_cast<uint64_t>(b.tune.wide_min), static_cast<uint64_t>(b.tune.max_split),
+          u(b.jm.t), static_cast<uint64_t>(b.jm.cap), u(b.fa.xi), u(b.fa.vi), u(b.fa.h2),
+          u(b.fa.islot), u(b.fa.nb_count), u(b.fa.nb_slot), u(b.part), u(b.nn_r2), u(b.nn_slot),
+          static_cast<uint64_t>(b.pcap), u(b.ibcnt), static_cast<uint64_t>(b.nbl), u(b.acc),
+          u(b.jerk), u(b.pot), u(b.r2nn), u(b.nnb), u(b.status), u(b.ovf_list), u(b.ovf_tag),
+          static_cast<uint64_t>(h.prec), static_cast<uint64_t>(grid), u(s)};
+}
+
+// Plan kernel + persistent kernel on stream s, either launched directly
+// (with the event `mid`, if any, recorded between them) or through a
+// captured graph that is replayed while every argument stays the same
+// (`mid` then recorded before the graph).
+int launch_batch_all(Handle &h, const BatchArgs &b, int grid, hipStream_t s, hipEvent_t mid) {
+  if (!h.use_graph) {
+    HIPCHK(&h, launch_batch_plan(b, s));
+    if (mid) HIPCHK(&h, hipEventRecord(mid, s));
+    HIPCHK(&h, launch_batch_force(h.prec, b, grid, s));
+    return 0;
+  }
+  if (mid) HIPCHK(&h, hipEventRecord(mid, s));
+  std::vector<uint64_t> key = graph_key(h, b, grid, s);
+  if (h.gexec && key == h.gkey) {
+    HIPCHK(&h, hipGraphLaunch(h.gexec, s));
+    return 0;
+  }
+  destroy_graph(h);
+  HIPCHK(&h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  hipError_t e = launch_batch_plan(b, s);
+  if (e == hipSuccess) e = launch_batch_force(h.prec, b, grid, s);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(s, &g);
+  if (e == hipSuccess) e = ec;
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(&h, e, "batch graph capture");
+  }
+  h.graph = g;
+  e = hipGraphInstantiate(&h.gexec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    h.gexec = nullptr;
+    destroy_graph(h);
+    return hip_fail(&h, e, "hipGraphInstantiate");
+  }
+  h.gkey = std::move(key);
+  HIPCHK(&h, hipGraphLaunch(h.gexec, s));
+  return 0;
+}
+
+// Enqueue a batch whose ncl descriptors are at d_cl (device memory).
+int enqueue_batch(Handle &h, int ncl, const g6mi_cluster *d_cl, int ni_total, const int *d_islot,
+                  const double *d_xi, const double *d_vi, const double *d_h2, double *d_acc,
+                  double *d_jerk, double *d_pot, int *d_nnb, double *d_r2nn, hipStream_t s) {
+  int rc = ensure_jmem(h, std::max<size_t>(1, h.n_contig));
+  if (rc) return rc;
+  rc = upload_dirty(h, s);
+  if (rc) return rc;
+  const size_t n = static_cast<size_t>(std::max(ni_total, 1));
+  BatchTune tune = h.btune;
+  const size_t fit = kBatchPartialBudget / (n * kPartialEntryBytes);
+  tune.max_split = static_cast<int>(std::max<size_t>(1, std::min<size_t>(tune.max_split, fit)));
+  const size_t item_cap = (n / 256 + static_cast<size_t>(ncl) + 1) * static_cast<size_t>(tune.max_split);
+  if (item_cap > static_cast<size_t>(INT_MAX)) return fail(&h, G6MI_EINVAL, "batch too large");
+  const size_t pcap = n * static_cast<size_t>(tune.max_split);
+  HIPCHK(&h, ensure(h.d_plan, std::max(ncl, 1) * sizeof(BatchPlan)));
+  HIPCHK(&h, ensure(h.d_items, item_cap * sizeof(int)));
+  HIPCHK(&h, ensure(h.d_bwork, sizeof(BatchWork)));
+  HIPCHK(&h, ensure(h.d_ibcnt, n * sizeof(int)));
+  HIPCHK(&h, ensure(h.d_part, 7 * pcap * sizeof(double)));
+  HIPCHK(&h, ensure(h.d_nnr2, pcap * sizeof(double)));
+  HIPCHK(&h, ensure(h.d_nnslot, pcap * sizeof(int)));
+  HIPCHK(&h, ensure(h.d_nbcount, n * sizeof(int)));
+  HIPCHK(&h, ensure(h.d_nblist, n * kNbMax * sizeof(int)));
+  HIPCHK(&h, ensure(h.d_flags, 64));
+  HIPCHK(&h, ensure(h.d_ovf, 2 * n * sizeof(int)));
+
+  BatchArgs b;
+  b.cl = d_cl;
+  b.plan = static_cast<BatchPlan *>(h.d_plan.p);
+  b.item_cl = static_cast<int *>(h.d_items.p);
+  b.work = static_cast<BatchWork *>(h.d_bwork.p);
+  b.ncl = ncl;
+  b.nj_set = static_cast<int>(h.n_contig);
+  b.ni_total = ni_total;
+  b.item_cap = static_cast<int>(item_cap);
+  b.tune = tune;
+  b.jm = h.jm;
+  b.fa.xi = d_xi;
+  b.fa.vi = d_vi;
+  b.fa.h2 = d_h2;
+  b.fa.islot = d_islot;
+  b.fa.ni = ni_total;
+  b.fa.nb_count = static_cast<int *>(h.d_nbcount.p);
+  b.fa.nb_slot = static_cast<int *>(h.d_nblist.p);
+  b.part = static_cast<double *>(h.d_part.p);
+  b.nn_r2 = static_cast<double *>(h.d_nnr2.p);
+  b.nn_slot = static_cast<int *>(h.d_nnslot.p);
+  b.pcap = pcap;
+  b.ibcnt = static_cast<int *>(h.d_ibcnt.p);
+  b.nbl = h.nbl ? 1 : 0;
+  b.acc = d_acc;
+  b.jerk = d_jerk;
+  b.pot = d_pot;
+  b.nnb = d_nnb;
+  b.r2nn = d_r2nn;
+  b.status = static_cast<int *>(h.d_flags.p);
+  b.ovf_list = static_cast<int *>(h.d_ovf.p);
+  b.ovf_tag = b.ovf_list + n;
+  const int grid = batch_grid(h, h.prec);
+
+  h.shape[0] = 0;
+  h.shape[1] = tune.max_split;
+  h.shape[2] = kTile;
+  h.shape[3] = grid;
+  hipEvent_t *ev = nullptr;
+  if (h.timing && h.n_timed < kTimingRing) {
+    if (static_cast<size_t>(h.n_timed) == h.evs.size()) {
+      std::array<hipEvent_t, 4> q{};
+      for (auto &e : q) HIPCHK(&h, hipEventCreate(&e));
+      h.evs.push_back(q);
+    }
+    ev = h.evs[h.n_timed].data();
+  }
+  if (ev) HIPCHK(&h, hipEventRecord(ev[0], s));
+  rc = launch_batch_all(h, b, grid, s, ev ? ev[1] : nullptr);
+  if (rc) return rc;
+  if (ev) {
+    HIPCHK(&h, hipEventRecord(ev[2], s));
+    HIPCHK(&h, hipEventRecord(ev[3], s));
+    ++h.n_timed;
+  }
+  h.c_nj = 0;
+  h.c_ni = ni_total;
+  h.c_eps2 = 0.0;
+  h.c_stream = s;
+  h.c_prec = h.prec;
+  h.c_nbl = h.nbl;
+  h.c_have = true;
+  h.c_batch = true;
+  h.c_bargs = b;
+  h.res_valid = false;
+  h.nb_read = false;
+  h.nb_exact_done = false;
+  return 0;
+}
+
+int check_batch_args(Handle *h, int ncl, int ni_total, const int *d_islot, const double *d_xi,
+                     const double *d_vi, const double *d_h2, const double *d_acc, const double *d_jerk,
+                     const double *d_pot) {
+  if (h->pending) return fail(h, G6MI_ESTATE, "a host-path calculation is pending");
+  if (ncl < 0 || ncl > kBatchMaxClusters) return fail(h, G6MI_EINVAL, "ncl out of range");
+  if (ni_total < 0 || ni_total > G6MI_NI_MAX) return fail(h, G6MI_EINVAL, "ni_total out of range");
+  if (ni_total > 0 && (!d_islot || !d_xi || !d_vi || !d_h2 || !d_acc || !d_jerk || !d_pot))
+    return fail(h, G6MI_EINVAL, "null device array");
+  return 0;
+}
+
+// Host-side check of descriptors: ranges inside the j-memory and the
+// i-arrays, finite times and softening, no two clusters sharing an i-row.
+int check_clusters(Handle *h, int ncl, const g6mi_cluster *cl, int ni_total) {
+  if (ncl > 0 && !cl) return fail(h, G6MI_EINVAL, "null cluster array");
+  std::vector<std::pair<int, int>> rows;
+  rows.reserve(ncl);
+  for (int c = 0; c < ncl; ++c) {
+    const g6mi_cluster &d = cl[c];
+    const std::string at = "cluster " + std::to_string(c) + ": ";
+    if (d.joff < 0 || d.nj < 0 || static_cast<long long>(d.joff) + d.nj > static_cast<long long>(h->n_contig))
+      return fail(h, G6MI_EINVAL, at + "j-slots outside the slots set from slot 0");
+    if (d.ioff < 0 || d.ni < 0 || static_cast<long long>(d.ioff) + d.ni > ni_total)
+      return fail(h, G6MI_EINVAL, at + "i-rows outside 0 .. ni_total-1");
+    if (!std::isfinite(d.ti) || !std::isfinite(d.eps2) || d.eps2 < 0.0)
+      return fail(h, G6MI_EINVAL, at + "ti and eps2 must be finite, eps2 >= 0");
+    if (d.ni > 0) rows.emplace_back(d.ioff, d.ioff + d.ni);
+  }
+  std::sort(rows.begin(), rows.end());
+  for (size_t k = 1; k < rows.size(); ++k)
+    if (rows[k].first < rows[k - 1].second) return fail(h, G6MI_EINVAL, "clusters share i-rows");
+  return 0;
+}
+
+// Copy host descriptors to the handle's device buffer on stream s.
+int upload_clusters(Handle &h, int ncl, const g6mi_cluster *cl, hipStream_t s) {
+  const size_t bytes = std::max(ncl, 1) * sizeof(g6mi_cluster);
+  if (h.cl_busy) {
+    HIPCHK(&h, hipEventSynchronize(h.cl_ev));
+    h.cl_busy = false;
+  }
+  HIPCHK(&h, ensure(h.h_cl, bytes));
+  HIPCHK(&h, ensure(h.d_cl, bytes));
+  if (!h.cl_ev) HIPCHK(&h, hipEventCreateWithFlags(&h.cl_ev, hipEventDisableTiming));
+  if (ncl > 0) std::memcpy(h.h_cl.p, cl, ncl * sizeof(g6mi_cluster));
+  HIPCHK(&h, hipMemcpyAsync(h.d_cl.p, h.h_cl.p, bytes, hipMemcpyHostToDevice, s));
+  HIPCHK(&h, hipEventRecord(h.cl_ev, s));
+  h.cl_busy = true;
+  return 0;
+}
+
 } // namespace
 
 // =========================================================== exported ABI
@@ -522,6 +764,7 @@ G6MI_API int g6_open(int id) {
   HIPCHK(&h, hipGetDeviceProperties(&prop, dev));
   h.ncu = prop.multiProcessorCount;
   h.clock_mhz = prop.clockRate / 1000;
+  h.arch = prop.gcnArchName;
   HIPCHK(&h, hipStreamCreateWithFlags(&h.stream, hipStreamNonBlocking));
   HIPCHK(&h, hipEventCreateWithFlags(&h.stage_ev, hipEventDisableTiming));
   h.prec = parse_precision(std::getenv("G6MI_PRECISION"), G6MI_PREC_DS);
@@ -536,11 +779,13 @@ G6MI_API int g6_close(int id) {
   (void)hipSetDevice(h->device);
   (void)hipStreamSynchronize(h->stream);
   if (h->c_stream && h->c_stream != h->stream) (void)hipStreamSynchronize(h->c_stream);
+  destroy_graph(*h);
   for (DevBuf *b : {&h->d_jm, &h->d_pred, &h->d_stage, &h->d_i, &h->d_out, &h->d_part,
                     &h->d_nnr2, &h->d_nnslot, &h->d_nbcount, &h->d_nblist, &h->d_flags,
-                    &h->d_ovf})
+                    &h->d_ovf, &h->d_cl, &h->d_plan, &h->d_items, &h->d_bwork, &h->d_ibcnt})
     b->release();
-  for (PinBuf *b : {&h->h_stage, &h->h_i, &h->h_out}) b->release();
+  for (PinBuf *b : {&h->h_stage, &h->h_i, &h->h_out, &h->h_cl}) b->release();
+  if (h->cl_ev) (void)hipEventDestroy(h->cl_ev);
   for (auto &q : h->evs)
     for (auto &ev : q) (void)hipEventDestroy(ev);
   if (h->stage_ev) (void)hipEventDestroy(h->stage_ev);
@@ -702,9 +947,12 @@ G6MI_API int g6_read_neighbour_list(int id) {
     int status[kStatusWords] = {0, 0};
     HIPCHK(h, hipMemcpy(status, h->d_flags.p, sizeof(status), hipMemcpyDeviceToHost));
     if (status[kStatusOverflowCount] > 0 && !h->nb_exact_done) {
-      HIPCHK(h, launch_nb_exact(h->c_prec, h->c_args, h->jm.index, static_cast<int *>(h->d_flags.p),
-                                static_cast<int *>(h->d_ovf.p), status[kStatusOverflowCount],
-                                h->c_stream));
+      if (h->c_batch)
+        HIPCHK(h, launch_batch_nb_exact(h->c_prec, h->c_bargs, status[kStatusOverflowCount], h->c_stream));
+      else
+        HIPCHK(h, launch_nb_exact(h->c_prec, h->c_args, h->jm.index, static_cast<int *>(h->d_flags.p),
+                                  static_cast<int *>(h->d_ovf.p), status[kStatusOverflowCount],
+                                  h->c_stream));
       HIPCHK(h, hipStreamSynchronize(h->c_stream));
       h->nb_exact_done = true;
     }
@@ -904,6 +1152,257 @@ G6MI_API int g6mi_calc_device(int id, int nj, int ni, const int *d_islot, const 
   h->res_valid = false;
   return enqueue_calc(*h, nj, ni, d_islot, d_xi, d_vi, d_h2, eps2, d_acc, d_jerk, d_pot, d_nnb,
                       d_r2nn, s);
+}
+
+G6MI_API int g6mi_last_status(int id, int *flags) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  if (!flags) return fail(h, G6MI_EINVAL, "null flags");
+  if (!h->c_have || h->pending) return fail(h, G6MI_ESTATE, "no completed calculation");
+  HIPCHK(h, hipSetDevice(h->device));
+  HIPCHK(h, hipStreamSynchronize(h->c_stream));
+  int st[kStatusWords] = {0, 0};
+  HIPCHK(h, hipMemcpy(st, h->d_flags.p, sizeof(st), hipMemcpyDeviceToHost));
+  *flags = st[kStatusFlags];
+  return G6MI_OK;
+}
+
+// ------------------------------------------------------------ batched calls
+
+G6MI_API int g6mi_batch_calc_device(int id, int ncl, const g6mi_cluster *d_cl, int ni_total,
+                                    const int *d_islot, const double *d_xi, const double *d_vi,
+                                    const double *d_h2, double *d_acc, double *d_jerk,
+                                    double *d_pot, int *d_nnb, double *d_r2nn, void *stream) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  int rc = check_batch_args(h, ncl, ni_total, d_islot, d_xi, d_vi, d_h2, d_acc, d_jerk, d_pot);
+  if (rc) return rc;
+  if (ncl > 0 && !d_cl) return fail(h, G6MI_EINVAL, "null cluster array");
+  HIPCHK(h, hipSetDevice(h->device));
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : h->stream;
+  return enqueue_batch(*h, ncl, d_cl, ni_total, d_islot, d_xi, d_vi, d_h2, d_acc, d_jerk, d_pot,
+                       d_nnb, d_r2nn, s);
+}
+
+G6MI_API int g6mi_batch_calc(int id, int ncl, const g6mi_cluster *cl, int ni_total,
+                             const int *d_islot, const double *d_xi, const double *d_vi,
+                             const double *d_h2, double *d_acc, double *d_jerk, double *d_pot,
+                             int *d_nnb, double *d_r2nn, void *stream) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  int rc = check_batch_args(h, ncl, ni_total, d_islot, d_xi, d_vi, d_h2, d_acc, d_jerk, d_pot);
+  if (!rc) rc = check_clusters(h, ncl, cl, ni_total);
+  if (rc) return rc;
+  HIPCHK(h, hipSetDevice(h->device));
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : h->stream;
+  rc = upload_clusters(*h, ncl, cl, s);
+  if (rc) return rc;
+  return enqueue_batch(*h, ncl, static_cast<const g6mi_cluster *>(h->d_cl.p), ni_total, d_islot, d_xi,
+                       d_vi, d_h2, d_acc, d_jerk, d_pot, d_nnb, d_r2nn, s);
+}
+
+G6MI_API int g6mi_batch_use_graph(int id, int on) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  h->use_graph = on != 0;
+  if (!h->use_graph) {
+    HIPCHK(h, hipSetDevice(h->device));
+    if (h->c_stream) HIPCHK(h, hipStreamSynchronize(h->c_stream));
+    destroy_graph(*h);
+  }
+  return G6MI_OK;
+}
+
+namespace {
+int check_tuning(Handle *h, const g6mi_batch_tuning *t) {
+  if (t->item_work < 1 || t->item_work > 1024 || t->wide_min < 1 || t->wg_per_cu < 0 || t->wg_per_cu > 8 ||
+      t->max_split < 1 || t->max_split > 4096)
+    return fail(h, G6MI_EINVAL, "tuning out of range");
+  return 0;
+}
+
+void apply_tuning(Handle &h, const g6mi_batch_tuning &t) {
+  h.btune.item_work = t.item_work;
+  h.btune.wide_min = t.wide_min;
+  h.btune.max_split = t.max_split;
+  h.b_wg_per_cu = t.wg_per_cu;
+}
+
+g6mi_batch_tuning current_tuning(const Handle &h) {
+  g6mi_batch_tuning t;
+  t.item_work = h.btune.item_work;
+  t.wide_min = h.btune.wide_min;
+  t.max_split = h.btune.max_split;
+  t.wg_per_cu = h.b_wg_per_cu;
+  return t;
+}
+
+// Tuning results of this process, by workload key.
+std::mutex g_tune_mu;
+std::unordered_map<std::string, g6mi_batch_tuning> g_tune;
+
+constexpr const char *kTuneTag = "g6mi-batch-tune-v1";
+
+int ilog2_floor(double v) { return v >= 1.0 ? static_cast<int>(std::floor(std::log2(v))) : -1; }
+
+// Workload key: device, variant, and the batch's size class (number of
+// clusters, log2 of pairs, i-particles and j-slots).
+std::string tune_key(const Handle &h, int ncl, const g6mi_cluster *cl) {
+  double pairs = 0.0, nj = 0.0, ni = 0.0;
+  for (int c = 0; c < ncl; ++c) {
+    pairs += static_cast<double>(cl[c].ni) * cl[c].nj;
+    nj += cl[c].nj;
+    ni += cl[c].ni;
+  }
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s/cu%d/p%d/nb%d/c%d/lp%d/li%d/lj%d", h.arch.empty() ? "gpu" : h.arch.c_str(),
+                h.ncu, h.prec, h.nbl ? 1 : 0, ncl, ilog2_floor(pairs), ilog2_floor(ni), ilog2_floor(nj));
+  std::string k(buf);
+  for (char &ch : k)
+    if (ch == ' ' || ch == '\t' || ch == '\n') ch = '_';
+  return k;
+}
+
+bool cache_lookup(const char *path, const std::string &key, g6mi_batch_tuning &t) {
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      t = it->second;
+      return true;
+    }
+  }
+  if (!path) return false;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return false;
+  bool found = false;
+  char line[1024];
+  while (std::fgets(line, sizeof(line), f)) {
+    char tag[64], k[512];
+    g6mi_batch_tuning v;
+    double ms = 0.0;
+    if (std::sscanf(line, "%63s %511s %d %d %d %d %lf", tag, k, &v.item_work, &v.wide_min, &v.wg_per_cu,
+                    &v.max_split, &ms) == 7 &&
+        key == k && std::string(tag) == kTuneTag) {
+      t = v; // the last entry for the key wins
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+} // namespace
+
+G6MI_API int g6mi_batch_set_tuning(int id, const g6mi_batch_tuning *t) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  g6mi_batch_tuning v;
+  if (t) {
+    int rc = check_tuning(h, t);
+    if (rc) return rc;
+    v = *t;
+  } else {
+    BatchTune d;
+    v.item_work = d.item_work;
+    v.wide_min = d.wide_min;
+    v.max_split = d.max_split;
+    v.wg_per_cu = 0;
+  }
+  apply_tuning(*h, v);
+  return G6MI_OK;
+}
+
+G6MI_API int g6mi_batch_get_tuning(int id, g6mi_batch_tuning *t) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  if (!t) return fail(h, G6MI_EINVAL, "null tuning");
+  *t = current_tuning(*h);
+  return G6MI_OK;
+}
+
+G6MI_API int g6mi_batch_autotune(int id, int ncl, const g6mi_cluster *cl, int ni_total,
+                                 const int *d_islot, const double *d_xi, const double *d_vi,
+                                 const double *d_h2, double *d_acc, double *d_jerk, double *d_pot,
+                                 int *d_nnb, double *d_r2nn, void *stream, const char *cache_path,
+                                 int reps, g6mi_batch_tuning *best) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  int rc = check_batch_args(h, ncl, ni_total, d_islot, d_xi, d_vi, d_h2, d_acc, d_jerk, d_pot);
+  if (!rc) rc = check_clusters(h, ncl, cl, ni_total);
+  if (rc) return rc;
+  if (!cache_path) cache_path = std::getenv("G6MI_TUNE_CACHE");
+  const std::string key = tune_key(*h, ncl, cl);
+  g6mi_batch_tuning found;
+  if (cache_lookup(cache_path, key, found) && check_tuning(h, &found) == 0) {
+    apply_tuning(*h, found);
+    if (best) *best = found;
+    return G6MI_OK;
+  }
+  HIPCHK(h, hipSetDevice(h->device));
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : h->stream;
+  rc = upload_clusters(*h, ncl, cl, s);
+  if (rc) return rc;
+  const g6mi_cluster *d_cl = static_cast<const g6mi_cluster *>(h->d_cl.p);
+  if (reps <= 0) reps = 3;
+  const bool graph = h->use_graph, timing = h->timing;
+  h->use_graph = false;
+  h->timing = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  const g6mi_batch_tuning base = current_tuning(*h);
+  g6mi_batch_tuning win = base;
+  double win_ms = INFINITY;
+  const int max_wg = batch_waves(h->prec);
+  for (int iw : {1, 2, 4, 8, 16})
+    for (int wm : {257, 512, 1024})
+      for (int wg = 1; wg <= max_wg && rc == 0; ++wg) {
+        g6mi_batch_tuning t = base;
+        t.item_work = iw;
+        t.wide_min = wm;
+        t.wg_per_cu = wg;
+        apply_tuning(*h, t);
+        for (int r = 0; r <= reps && rc == 0; ++r) { // one untimed run, then reps timed
+          if (r == 1 && hipEventRecord(e0, s) != hipSuccess) rc = fail(h, G6MI_EDEVICE, "event");
+          if (!rc)
+            rc = enqueue_batch(*h, ncl, d_cl, ni_total, d_islot, d_xi, d_vi, d_h2, d_acc, d_jerk, d_pot, d_nnb,
+                               d_r2nn, s);
+        }
+        if (rc) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          rc = fail(h, G6MI_EDEVICE, "autotune timing");
+          break;
+        }
+        const double per = ms / reps;
+        if (per < win_ms) {
+          win_ms = per;
+          win = t;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->use_graph = graph;
+  h->timing = timing;
+  if (rc) {
+    apply_tuning(*h, base);
+    return rc;
+  }
+  apply_tuning(*h, win);
+  if (best) *best = win;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = win;
+  }
+  if (cache_path) {
+    FILE *f = std::fopen(cache_path, "a");
+    if (!f) return fail(h, G6MI_WARN, std::string("cannot append to tuning cache ") + cache_path);
+    std::fprintf(f, "%s %s %d %d %d %d %.6f\n", kTuneTag, key.c_str(), win.item_work, win.wide_min,
+                 win.wg_per_cu, win.max_split, win_ms);
+    std::fclose(f);
+  }
+  return G6MI_OK;
 }
 
 G6MI_API int g6mi_device_info(int id, int info[2]) {

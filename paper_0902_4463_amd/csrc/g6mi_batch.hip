@@ -1,0 +1,328 @@
+// Batched multi-cluster force evaluation: many independent systems of
+// uneven size and uneven active blocks in one launch.
+//
+//   batch_plan_kernel  -- one workgroup turns the cluster descriptors into a
+//                         per-cluster launch plan (i-particles per workgroup,
+//                         j-splits) and a flat list of work items
+//                         (cluster, i-block, j-split); the other workgroups
+//                         clear the per-row counters of the calculation.
+//   batch_kernel       -- persistent workgroups take items from a work queue
+//                         (one atomic counter).  An item predicts its j-tiles
+//                         straight into LDS from the float64 j-memory (the
+//                         predictor of Sec. 2.2 fused into the tile load),
+//                         runs the interaction of Sec. 2.3 on them and stores
+//                         its split partials; the last split of an i-block to
+//                         finish adds the partials of all splits in split
+//                         order and writes the results (the reduction of
+//                         Sec. 2.3 fused into the same launch).
+//   batch_nb_exact     -- exact neighbour lists for overflowed i-particles.
+//
+// Each cluster is what the paper's library evaluates per call; batching them
+// fills the 256 compute units when every single cluster is far too small to
+// do so, and removes the per-call launches.
+
+#include "g6mi_device.h"
+
+namespace g6mi {
+
+// -------------------------------------------------------------------- plan
+
+// Work items: for cluster c with ni i-particles in nib i-blocks of ipw and
+// ntiles j-tiles in nsplit splits of `per` tiles, nib * nsplit items.  The
+// tiles per split are chosen so that every item costs about
+// item_work * 512 * kTile pair evaluations per lane group: one tile costs a
+// lane ipw pairs (narrow blocks) or 512 (wide blocks).
+__global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
+  const int tid = threadIdx.x;
+  if (blockIdx.x > 0) {
+    // rows (blockIdx.x - 1) * chunk ...: i-block arrival counters (at most
+    // one i-block per row) and neighbour counts
+    const int base = (blockIdx.x - 1) * kPlanZeroChunk;
+    for (int k = tid; k < kPlanZeroChunk; k += 256) {
+      const int r = base + k;
+      if (r < b.ni_total) {
+        b.ibcnt[r] = 0;
+        if (b.nbl) b.fa.nb_count[r] = 0;
+      }
+    }
+    return;
+  }
+  __shared__ int s_items[256], s_nib[256];
+  __shared__ long long s_pent[256], s_rows[256];
+  __shared__ int s_flags;
+  if (tid == 0) s_flags = 0;
+  __syncthreads();
+  // inclusive scans over one chunk of 256 clusters
+  auto scan = [&](auto *a) {
+    for (int off = 1; off < 256; off <<= 1) {
+      const auto x = tid >= off ? a[tid - off] : 0;
+      __syncthreads();
+      a[tid] += x;
+      __syncthreads();
+    }
+  };
+  int c_items = 0, c_nib = 0; // totals of the chunks before
+  long long c_pent = 0, c_rows = 0;
+  for (int c0 = 0; c0 < b.ncl; c0 += 256) {
+    const int c = c0 + tid;
+    int ni = 0, nj = 0;
+    bool ok = false;
+    if (c < b.ncl) {
+      const g6mi_cluster d = b.cl[c];
+      ok = d.joff >= 0 && d.nj >= 0 && static_cast<long long>(d.joff) + d.nj <= b.nj_set && d.ioff >= 0 &&
+           d.ni >= 0 && static_cast<long long>(d.ioff) + d.ni <= b.ni_total && isfinite(d.ti) &&
+           isfinite(d.eps2) && d.eps2 >= 0.0;
+      ni = ok ? d.ni : 0;
+      nj = ok ? d.nj : 0;
+    }
+    // Clusters sharing i-rows could add up to more rows than ni_total, and
+    // the i-block counters and partial sums are sized by ni_total: every
+    // cluster past that many rows in total is skipped.
+    s_rows[tid] = ni;
+    __syncthreads();
+    scan(s_rows);
+    if (ok && c_rows + s_rows[tid] > b.ni_total) {
+      ok = false;
+      ni = nj = 0;
+    }
+    if (c < b.ncl && !ok) atomicOr(&s_flags, kFlagBadCluster);
+    int ipw = 1, l2 = 0;
+    if (ni >= b.tune.wide_min) {
+      ipw = 2 * kWG;
+      l2 = 9;
+    } else {
+      while (ipw < ni && ipw < kWG) {
+        ipw <<= 1;
+        ++l2;
+      }
+    }
+    const int nib = ni > 0 ? (ni + ipw - 1) / ipw : 0;
+    const int ntiles = (nj + kTile - 1) / kTile;
+    const int want = max(1, b.tune.item_work * (2 * kWG) / ipw);
+    int per = max(1, min(ntiles, want));
+    int nsplit = ntiles > 0 ? (ntiles + per - 1) / per : 1;
+    if (nsplit > b.tune.max_split) {
+      per = (ntiles + b.tune.max_split - 1) / b.tune.max_split;
+      nsplit = (ntiles + per - 1) / per;
+    }
+    const long long pent = static_cast<long long>(ni) * nsplit;
+    s_items[tid] = nib * nsplit;
+    s_nib[tid] = nib;
+    s_pent[tid] = pent;
+    __syncthreads();
+    scan(s_items);
+    scan(s_nib);
+    scan(s_pent);
+    if (c < b.ncl) {
+      BatchPlan pl;
+      pl.ipw = ipw;
+      pl.log2ipw = l2;
+      pl.nsplit = nsplit;
+      pl.per = per;
+      pl.nib = nib;
+      pl.ib0 = c_nib + s_nib[tid] - nib;
+      pl.item0 = c_items + s_items[tid] - nib * nsplit;
+      pl.pad = 0;
+      pl.pbase = c_pent + s_pent[tid] - pent;
+      b.plan[c] = pl;
+    }
+    c_items += s_items[255];
+    c_nib += s_nib[255];
+    c_pent += s_pent[255];
+    c_rows += s_rows[255];
+    __syncthreads();
+  }
+  // item -> cluster table; each thread fills the items of its own clusters
+  // (a thread reads back only the plan entries it wrote itself)
+  for (int c = tid; c < b.ncl; c += 256) {
+    const BatchPlan pl = b.plan[c];
+    const int end = min(pl.item0 + pl.nib * pl.nsplit, b.item_cap);
+    for (int q = pl.item0; q < end; ++q) b.item_cl[q] = c;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    b.work->head = 0;
+    b.work->nitems = min(c_items, b.item_cap);
+    b.work->nib = c_nib;
+    // more items than the table holds cannot happen with the host's bound;
+    // it would drop work, so it is reported like a bad descriptor
+    b.status[kStatusFlags] = s_flags | (c_items > b.item_cap ? kFlagBadCluster : 0);
+    b.status[kStatusOverflowCount] = 0;
+  }
+}
+
+// ------------------------------------------------------ persistent kernel
+
+__device__ __forceinline__ void store_partial(const BatchArgs &b, size_t e, const Totals &t, double best,
+                                              int bslot) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    b.part[d * b.pcap + e] = t.acc[d];
+    b.part[(3 + d) * b.pcap + e] = t.jrk[d];
+  }
+  b.part[6 * b.pcap + e] = t.pot;
+  b.nn_r2[e] = best;
+  b.nn_slot[e] = bslot;
+}
+
+// Persistent workgroups: take the next item until the queue is empty (every
+// wave reaches the exit: items are finite and each workgroup takes one item
+// per round).  Partial entry of i-particle il (cluster row) in split s:
+// pbase + s * ni + il, component-major over pcap entries.
+template <int PREC, bool NBL>
+__global__ __launch_bounds__(kWG, wide_waves<PREC>()) void batch_kernel(BatchArgs b) {
+  using R = real_t<PREC>;
+  constexpr int REC = rec4<PREC>();
+  __shared__ __attribute__((aligned(16))) unsigned char lds[narrow_lds_bytes<PREC>()];
+  __shared__ int s_item, s_last;
+  float4 *tile = reinterpret_cast<float4 *>(lds);
+  const int tid = threadIdx.x;
+  const int nitems = b.work->nitems;
+
+  for (;;) {
+    __syncthreads(); // the previous item is done with the LDS and s_item
+    if (tid == 0) s_item = atomicAdd(&b.work->head, 1);
+    __syncthreads();
+    // uniform across the workgroup: the item's cluster, descriptor and plan
+    // are then scalar loads held in scalar registers
+    const int q = __builtin_amdgcn_readfirstlane(s_item);
+    if (q >= nitems) break;
+    const int c = b.item_cl[q];
+    const g6mi_cluster d = b.cl[c];
+    const BatchPlan p = b.plan[c];
+    const int r = q - p.item0;
+    const int ib = r / p.nsplit;
+    const int sp = r - ib * p.nsplit;
+    const int ntiles = (d.nj + kTile - 1) / kTile;
+    const int tb = sp * p.per;
+    const int te = min(ntiles, tb + p.per);
+    const int jend = d.joff + d.nj;
+    const R eps2 = static_cast<R>(d.eps2);
+    const size_t e0 = static_cast<size_t>(p.pbase) + static_cast<size_t>(sp) * d.ni;
+
+    if (p.ipw == 2 * kWG) {
+      const int il0 = ib * (2 * kWG) + tid, il1 = il0 + kWG;
+      WideLanes<PREC, NBL> w;
+      w.init(b.fa, d.ioff + il0, d.ioff + il1, il0 < d.ni, il1 < d.ni);
+      for (int tt = tb; tt < te; ++tt) {
+        const int jbase = d.joff + tt * kTile;
+        const int cnt = min(kTile, jend - jbase);
+        __syncthreads();
+        if (tid < cnt) predict_record<PREC>(b.jm, static_cast<size_t>(jbase + tid), d.ti, tile + tid * REC);
+        __syncthreads();
+        w.tile(tile, jbase, cnt, eps2, b.fa.nb_count, b.fa.nb_slot);
+        w.resolve(tile, jbase); // while the tile is still in LDS
+      }
+      if (w.v0) store_partial(b, e0 + il0, w.t0, static_cast<double>(w.ebest0), w.eslot0);
+      if (w.v1) store_partial(b, e0 + il1, w.t1, static_cast<double>(w.ebest1), w.eslot1);
+    } else {
+      const int ipw = p.ipw;
+      const int lil = tid & (ipw - 1);
+      const int il = ib * ipw + lil;
+      NarrowLane<PREC, NBL> n;
+      n.init(b.fa, d.ioff + il, il < d.ni, tid >> p.log2ipw, 8 - p.log2ipw);
+      for (int tt = tb; tt < te; ++tt) {
+        const int jbase = d.joff + tt * kTile;
+        const int cnt = min(kTile, jend - jbase);
+        __syncthreads();
+        if (tid < cnt) predict_record<PREC>(b.jm, static_cast<size_t>(jbase + tid), d.ti, tile + tid * REC);
+        __syncthreads();
+        n.tile(tile, jbase, cnt, eps2, b.fa.nb_count, b.fa.nb_slot);
+        n.resolve(tile, jbase);
+      }
+      double bestd;
+      int bslot;
+      n.lane_sum(reinterpret_cast<double *>(lds), tid, lil, ipw, bestd, bslot);
+      if (n.sub == 0 && n.valid) store_partial(b, e0 + il, n.t, bestd, bslot);
+    }
+
+    // The last split of the i-block to arrive finishes its i-particles.
+    // Release: every lane's partial and neighbour stores are made visible
+    // device-wide before the arrival is counted; acquire on the other side.
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_last = atomicAdd(b.ibcnt + p.ib0 + ib, 1) == p.nsplit - 1;
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(s_last)) {
+      __threadfence();
+      const int ipw = p.ipw;
+      int fl = 0;
+      for (int k = tid; k < ipw; k += kWG) {
+        const int il = ib * ipw + k;
+        if (il < d.ni) {
+          const size_t e = static_cast<size_t>(p.pbase) + il;
+          fl |= finish_row(p.nsplit, b.part + e, static_cast<size_t>(d.ni), b.pcap, b.nn_r2 + e, b.nn_slot + e,
+                           static_cast<size_t>(d.ni), d.ioff + il, b.jm.index, b.fa.nb_count, b.fa.nb_slot, NBL,
+                           b.acc, b.jerk, b.pot, b.nnb, b.r2nn, b.status, b.ovf_list, b.ovf_tag, c);
+        }
+      }
+      if (fl) atomicOr(b.status + kStatusFlags, fl);
+    }
+  }
+}
+
+// ------------------------------------------------- neighbour-list overflow
+
+// One workgroup per queued i-particle: its list rebuilt from the slots of
+// its own cluster, each record predicted again exactly as in batch_kernel.
+template <int PREC>
+__global__ __launch_bounds__(kWG) void batch_nb_exact_kernel(BatchArgs b) {
+  __shared__ unsigned s_cnt;
+  __shared__ int s_keep[kNbMax];
+  const int novf = b.status[kStatusOverflowCount];
+  for (int q = blockIdx.x; q < novf; q += gridDim.x) {
+    const int row = b.ovf_list[q];
+    const g6mi_cluster d = b.cl[b.ovf_tag[q]];
+    IState<PREC> st;
+    int slot;
+    real_t<PREC> h2;
+    load_i<PREC>(st, b.fa, row, true, slot, h2);
+    const JMem jm = b.jm;
+    const double ti = d.ti;
+    auto rec_of = [jm, ti](int js, float4 *buf) -> const float4 * {
+      predict_record<PREC>(jm, static_cast<size_t>(js), ti, buf);
+      return buf;
+    };
+    exact_list<PREC>(st, slot, h2, d.joff, d.joff + d.nj, jm.index, rec_of,
+                     b.fa.nb_slot + static_cast<size_t>(row) * kNbMax, s_cnt, s_keep);
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_batch_plan(const BatchArgs &b, hipStream_t s) {
+  const unsigned zero_blocks = static_cast<unsigned>((b.ni_total + kPlanZeroChunk - 1) / kPlanZeroChunk);
+  hipLaunchKernelGGL(batch_plan_kernel, dim3(1 + zero_blocks), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+template <int PREC>
+static void launch_batch_prec(const BatchArgs &b, int grid, hipStream_t s) {
+  if (b.nbl)
+    hipLaunchKernelGGL((batch_kernel<PREC, true>), dim3(grid), dim3(kWG), 0, s, b);
+  else
+    hipLaunchKernelGGL((batch_kernel<PREC, false>), dim3(grid), dim3(kWG), 0, s, b);
+}
+
+hipError_t launch_batch_force(int prec, const BatchArgs &b, int grid, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  switch (prec) {
+  case G6MI_PREC_FP32: launch_batch_prec<G6MI_PREC_FP32>(b, grid, s); break;
+  case G6MI_PREC_DS: launch_batch_prec<G6MI_PREC_DS>(b, grid, s); break;
+  default: launch_batch_prec<G6MI_PREC_FP64>(b, grid, s);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_nb_exact(int prec, const BatchArgs &b, int novf, hipStream_t s) {
+  if (novf <= 0) return hipSuccess;
+  const dim3 grid(static_cast<unsigned>(novf < 1024 ? novf : 1024));
+  switch (prec) {
+  case G6MI_PREC_FP32: hipLaunchKernelGGL(batch_nb_exact_kernel<G6MI_PREC_FP32>, grid, dim3(kWG), 0, s, b); break;
+  case G6MI_PREC_DS: hipLaunchKernelGGL(batch_nb_exact_kernel<G6MI_PREC_DS>, grid, dim3(kWG), 0, s, b); break;
+  default: hipLaunchKernelGGL(batch_nb_exact_kernel<G6MI_PREC_FP64>, grid, dim3(kWG), 0, s, b);
+  }
+  return hipGetLastError();
+}
+
+} // namespace g6mi

@@ -1,0 +1,771 @@
+// Device-side building blocks shared by the single-system kernels
+// (g6mi_kernels.hip) and the batched multi-cluster kernel (g6mi_batch.hip):
+// the j-predictor of one record, the pair interaction in the three precision
+// variants, the two-level float32 summation, and the per-lane state that
+// walks LDS-staged j-tiles (two i-particles per lane, or one i-particle
+// shared by L lanes).
+#pragma once
+
+#include "g6mi_internal.h"
+#include "../../include/g6mi.h"
+
+#include <cmath>
+#include <cfloat>
+#include <type_traits>
+
+namespace g6mi {
+
+// j-records per group: the unit of the nearest-neighbour bookkeeping, of the
+// neighbour-list flags and of the first level of float32 summation.
+constexpr int kGroup = G6MI_GROUP;
+static_assert(kTile / kGroup <= 32, "one mask bit per group");
+static_assert(kTile % kGroup == 0, "whole groups per tile");
+static_assert(kTile == kWG, "one j-record per lane when a tile is predicted in place");
+
+// Predicted record size in float4 units.
+template <int PREC> constexpr int rec4() {
+  return PREC == G6MI_PREC_DS ? 3 : (PREC == G6MI_PREC_FP32 ? 2 : 4);
+}
+
+template <int PREC> using real_t = std::conditional_t<PREC == G6MI_PREC_FP64, double, float>;
+
+// ---------------------------------------------------------------- predictor
+
+// Sec. 2.2, Eq. (1) and (2), with the stored coefficients a2 = a/2 and
+// j6 = jerk/6 and tau = t_i - t_j, evaluated by Horner's rule in float64.
+// The double-single split (Sec. 2.2, Bailey's format) is hi = fl32(x),
+// lo = fl32(x - hi); x - hi is exact in float64.  Writes the record of slot
+// k in the layout of the precision variant to o (global memory or LDS).
+template <int PREC>
+__device__ __forceinline__ void predict_record(const JMem &jm, size_t k, double ti,
+                                               float4 *__restrict__ o) {
+  const double tau = ti - jm.t[k];
+  double xp[3], vp[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const size_t e = d * jm.cap + k;
+    const double c2 = jm.a2[e], c3 = jm.j6[e], c1 = jm.v[e];
+    xp[d] = jm.x[e] + tau * (c1 + tau * (c2 + tau * c3));
+    vp[d] = c1 + tau * (2.0 * c2 + tau * (3.0 * c3));
+  }
+  const double mk = jm.m[k];
+  if constexpr (PREC == G6MI_PREC_DS) {
+    float hi[3], lo[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      hi[d] = static_cast<float>(xp[d]);
+      lo[d] = static_cast<float>(xp[d] - static_cast<double>(hi[d]));
+    }
+    o[0] = make_float4(hi[0], hi[1], hi[2], static_cast<float>(mk));
+    o[1] = make_float4(lo[0], lo[1], lo[2], 0.0f);
+    o[2] = make_float4(static_cast<float>(vp[0]), static_cast<float>(vp[1]),
+                       static_cast<float>(vp[2]), 0.0f);
+  } else if constexpr (PREC == G6MI_PREC_FP32) {
+    o[0] = make_float4(static_cast<float>(xp[0]), static_cast<float>(xp[1]),
+                       static_cast<float>(xp[2]), static_cast<float>(mk));
+    o[1] = make_float4(static_cast<float>(vp[0]), static_cast<float>(vp[1]),
+                       static_cast<float>(vp[2]), 0.0f);
+  } else {
+    double2 *o2 = reinterpret_cast<double2 *>(o);
+    o2[0] = make_double2(xp[0], xp[1]);
+    o2[1] = make_double2(xp[2], mk);
+    o2[2] = make_double2(vp[0], vp[1]);
+    o2[3] = make_double2(vp[2], 0.0);
+  }
+}
+
+// ------------------------------------------------------------- interaction
+
+// 1/sqrt(s) in float64: the hardware estimate refined by two Newton-Raphson
+// steps, y <- y + y (1 - s y^2) / 2, each roughly doubling the correct bits.
+__device__ __forceinline__ double rsqrt_f64(double s) {
+  double y = __builtin_amdgcn_rsq(s);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-s * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+// Per-lane position and velocity of one i-particle.
+template <int PREC> struct IState;
+
+template <> struct IState<G6MI_PREC_DS> {
+  float xh[3], xl[3], v[3];
+};
+template <> struct IState<G6MI_PREC_FP32> {
+  float x[3], v[3];
+};
+template <> struct IState<G6MI_PREC_FP64> {
+  double x[3], v[3];
+};
+
+// Running sums of one i-particle's pair terms: acceleration, the two jerk
+// parts (m w / r^3 and m (r.w) r / r^5) and m / r.
+//
+// Float32 variants sum in two levels before the float64 totals: a fresh
+// group of kGroup pairs, then the group sums into the tile sums.  A close
+// neighbour's term can exceed the far-field terms by 10^4 or more; added one
+// by one to a partial sum holding it, terms below half its ulp would round
+// away entirely, a systematic loss up to ~1e-5.  Within a group at most
+// kGroup - 1 terms meet such a partial, and group sums are large enough to
+// round rather than vanish.
+template <class R> struct Sums {
+  R a[3], j1[3], j2[3], p;
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a[k] = j1[k] = j2[k] = R(0);
+    p = R(0);
+  }
+  __device__ __forceinline__ void add(const Sums &o) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      a[k] += o.a[k];
+      j1[k] += o.j1[k];
+      j2[k] += o.j2[k];
+    }
+    p += o.p;
+  }
+};
+
+// Separation of i and one j-record: r = x_j - x_i (Eq. (3) for DS), the
+// velocity difference and r^2 without softening.
+template <int PREC>
+__device__ __forceinline__ void separation(const IState<PREC> &st, const float4 *__restrict__ rec,
+                                           real_t<PREC> d[3], real_t<PREC> w[3], real_t<PREC> &mj) {
+  if constexpr (PREC == G6MI_PREC_DS) {
+    const float4 p = rec[0], q = rec[1], v = rec[2];
+    d[0] = (p.x - st.xh[0]) + (q.x - st.xl[0]);
+    d[1] = (p.y - st.xh[1]) + (q.y - st.xl[1]);
+    d[2] = (p.z - st.xh[2]) + (q.z - st.xl[2]);
+    w[0] = v.x - st.v[0];
+    w[1] = v.y - st.v[1];
+    w[2] = v.z - st.v[2];
+    mj = p.w;
+  } else if constexpr (PREC == G6MI_PREC_FP32) {
+    const float4 p = rec[0], v = rec[1];
+    d[0] = p.x - st.x[0];
+    d[1] = p.y - st.x[1];
+    d[2] = p.z - st.x[2];
+    w[0] = v.x - st.v[0];
+    w[1] = v.y - st.v[1];
+    w[2] = v.z - st.v[2];
+    mj = p.w;
+  } else {
+    const double2 *r2 = reinterpret_cast<const double2 *>(rec);
+    const double2 p0 = r2[0], p1 = r2[1], w0 = r2[2], w1 = r2[3];
+    d[0] = p0.x - st.x[0];
+    d[1] = p0.y - st.x[1];
+    d[2] = p1.x - st.x[2];
+    w[0] = w0.x - st.v[0];
+    w[1] = w0.y - st.v[1];
+    w[2] = w1.x - st.v[2];
+    mj = p1.y;
+  }
+}
+
+// r^2 in one fixed expression, so that every path takes the same neighbour
+// decisions for the same pair
+template <int PREC>
+__device__ __forceinline__ real_t<PREC> sq3(const real_t<PREC> d[3]) {
+  return fma(d[2], d[2], fma(d[1], d[1], d[0] * d[0]));
+}
+
+template <int PREC>
+__device__ __forceinline__ real_t<PREC> r2_of(const IState<PREC> &st, const float4 *__restrict__ rec) {
+  real_t<PREC> d[3], w[3], mj;
+  separation<PREC>(st, rec, d, w, mj);
+  return sq3<PREC>(d);
+}
+
+// One pair (i, j).  MASK: compare the j-slot with the i-particle's own slot
+// and drop the self pair.  NBL: build neighbour lists.
+template <int PREC, bool MASK, bool NBL>
+__device__ __forceinline__ void pair(const IState<PREC> &st, Sums<real_t<PREC>> &acc,
+                                     const float4 *__restrict__ rec,
+                                     int jslot, int islot, real_t<PREC> eps2,
+                                     real_t<PREC> h2, real_t<PREC> &best, int &bslot,
+                                     int *__restrict__ nb_count, int *__restrict__ nb_row) {
+  using R = real_t<PREC>;
+  R d[3], w[3], mj;
+  separation<PREC>(st, rec, d, w, mj);
+  const R dx = d[0], dy = d[1], dz = d[2], dvx = w[0], dvy = w[1], dvz = w[2];
+  R r2u = sq3<PREC>(d);
+  R s = r2u + eps2;
+  if constexpr (MASK) {
+    const bool self = (jslot == islot);
+    mj = self ? R(0) : mj;
+    s = self ? R(1) : s;
+    r2u = self ? R(INFINITY) : r2u;
+  }
+  R rinv;
+  if constexpr (PREC == G6MI_PREC_FP64) rinv = rsqrt_f64(s);
+  else rinv = __builtin_amdgcn_rsqf(s);
+  const R rinv2 = rinv * rinv;
+  const R mr = mj * rinv;          // m / r
+  const R mr3 = mr * rinv2;        // m / r^3
+  const R rv = dx * dvx + dy * dvy + dz * dvz;
+  const R mr3t = mr3 * (rv * rinv2); // m (r.v) / r^5
+  acc.p += mr;
+  acc.a[0] += mr3 * dx;
+  acc.a[1] += mr3 * dy;
+  acc.a[2] += mr3 * dz;
+  acc.j1[0] += mr3 * dvx;
+  acc.j1[1] += mr3 * dvy;
+  acc.j1[2] += mr3 * dvz;
+  acc.j2[0] += mr3t * dx;
+  acc.j2[1] += mr3t * dy;
+  acc.j2[2] += mr3t * dz;
+  if (r2u < best) { // strict: the first (lowest) slot wins a tie
+    best = r2u;
+    bslot = jslot;
+  }
+  if constexpr (NBL) {
+    if (r2u < h2) {
+      const int pos = atomicAdd(nb_count, 1);
+      if (pos < kNbMax) nb_row[pos] = jslot;
+    }
+  }
+}
+
+// The pair terms of Sec. 2.3 added to `acc`; returns r^2 (without
+// softening) for the neighbour search.  No self test: the caller only uses
+// it on tiles that hold no i-particle's own slot.  FIRST: the group's first
+// pair sets the sums instead of adding to them.
+template <int PREC, bool FIRST = false>
+__device__ __forceinline__ real_t<PREC> pair_core(const IState<PREC> &st, Sums<real_t<PREC>> &acc,
+                                                  const float4 *__restrict__ rec, real_t<PREC> eps2) {
+  using R = real_t<PREC>;
+  R d[3], w[3], mj;
+  separation<PREC>(st, rec, d, w, mj);
+  const R r2u = sq3<PREC>(d);
+  const R s = r2u + eps2;
+  R rinv;
+  if constexpr (PREC == G6MI_PREC_FP64) rinv = rsqrt_f64(s);
+  else rinv = __builtin_amdgcn_rsqf(s);
+  const R rinv2 = rinv * rinv;
+  const R mr = mj * rinv;
+  const R mr3 = mr * rinv2;
+  const R rv = d[0] * w[0] + d[1] * w[1] + d[2] * w[2];
+  const R mr3t = mr3 * (rv * rinv2);
+  if constexpr (FIRST) {
+    acc.p = mr;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      acc.a[k] = mr3 * d[k];
+      acc.j1[k] = mr3 * w[k];
+      acc.j2[k] = mr3t * d[k];
+    }
+  } else {
+    acc.p += mr;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      acc.a[k] += mr3 * d[k];
+      acc.j1[k] += mr3 * w[k];
+      acc.j2[k] += mr3t * d[k];
+    }
+  }
+  return r2u;
+}
+
+// i-particle `row` of the i-arrays in a's layout.  An invalid row (a padding
+// lane) gets the origin, no own slot and h2 = -inf (no neighbours); its
+// results are never stored.
+template <int PREC>
+__device__ __forceinline__ void load_i(IState<PREC> &st, const ForceArgs &a, int row, bool valid,
+                                       int &islot, real_t<PREC> &h2) {
+  using R = real_t<PREC>;
+  double xi[3] = {0.0, 0.0, 0.0}, vi[3] = {0.0, 0.0, 0.0};
+  islot = -1;
+  h2 = R(-INFINITY);
+  if (valid) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      xi[d] = a.xi[3 * static_cast<size_t>(row) + d];
+      vi[d] = a.vi[3 * static_cast<size_t>(row) + d];
+    }
+    islot = a.islot[row];
+    h2 = static_cast<R>(a.h2[row]);
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if constexpr (PREC == G6MI_PREC_DS) {
+      st.xh[d] = static_cast<float>(xi[d]);
+      st.xl[d] = static_cast<float>(xi[d] - static_cast<double>(st.xh[d]));
+      st.v[d] = static_cast<float>(vi[d]);
+    } else {
+      st.x[d] = static_cast<R>(xi[d]);
+      st.v[d] = static_cast<R>(vi[d]);
+    }
+  }
+}
+
+// Float64 running totals of one i-particle: the tile sums are folded in
+// after every tile (float32 variants sum at most kTile terms in float32).
+struct Totals {
+  double acc[3], jrk[3], pot;
+};
+
+template <class R>
+__device__ __forceinline__ void fold(Sums<R> &ts, Totals &t) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    t.acc[d] += static_cast<double>(ts.a[d]);
+    t.jrk[d] += static_cast<double>(ts.j1[d]) - 3.0 * static_cast<double>(ts.j2[d]);
+  }
+  t.pot += static_cast<double>(ts.p);
+  ts.zero();
+}
+
+// Per-pair path for tiles holding an own slot or the ragged end: the pair
+// terms go through group sums of kGroup pairs (float32 variants) before the
+// tile sums, as on the grouped path.
+template <int PREC, bool NBL>
+struct MaskedRun {
+  using R = real_t<PREC>;
+  Sums<R> g;
+  int n = 0;
+  __device__ __forceinline__ void start() {
+    g.zero();
+    n = 0;
+  }
+  __device__ __forceinline__ void step(const IState<PREC> &st, Sums<R> &ts, const float4 *rec, int jslot,
+                                       int islot, R eps2, R h2, R &best, int &bslot, int *nb_count,
+                                       int *nb_row) {
+    if constexpr (PREC == G6MI_PREC_FP64) {
+      pair<PREC, true, NBL>(st, ts, rec, jslot, islot, eps2, h2, best, bslot, nb_count, nb_row);
+    } else {
+      pair<PREC, true, NBL>(st, g, rec, jslot, islot, eps2, h2, best, bslot, nb_count, nb_row);
+      if (++n == kGroup) {
+        ts.add(g);
+        start();
+      }
+    }
+  }
+  __device__ __forceinline__ void finish(Sums<R> &ts) {
+    if constexpr (PREC != G6MI_PREC_FP64) ts.add(g);
+  }
+};
+
+__device__ __forceinline__ void nb_append(int *__restrict__ nb_count, int *__restrict__ nb_slot,
+                                          int row, int jslot) {
+  const int pos = atomicAdd(nb_count + row, 1);
+  if (pos < kNbMax) nb_slot[static_cast<size_t>(row) * kNbMax + pos] = jslot;
+}
+
+// Exact slot of a grouped-path nearest neighbour: re-examine the kGroup
+// records of the group starting at slot grp (records grp, grp + stride, ...)
+// and merge the lexicographic (r^2, slot) minimum into (best, bslot).  The
+// record of slot js is at src + (js - base) records.  Clears grp.
+template <int PREC>
+__device__ __forceinline__ void resolve_group(const IState<PREC> &st, int &grp, int stride,
+                                              const float4 *__restrict__ src, int base,
+                                              real_t<PREC> &best, int &bslot) {
+  constexpr int REC = rec4<PREC>();
+  if (grp < 0) return;
+  for (int u = 0; u < kGroup; ++u) {
+    const int js = grp + u * stride;
+    const real_t<PREC> r = r2_of<PREC>(st, src + static_cast<size_t>(js - base) * REC);
+    if (r < best || (r == best && js < bslot)) {
+      best = r;
+      bslot = js;
+    }
+  }
+  grp = -1;
+}
+
+// ------------------------------------------- two i-particles per lane
+
+// Lane state of a wide block: every lane owns two i-particles (rows row0 and
+// row1 of the i-arrays) and every lane of a wave reads the same j-record
+// from LDS (a broadcast), so one LDS record serves 128 pairs.
+//
+// The j-loop runs in groups of kGroup records.  Nearest neighbour: one
+// min() per pair; once per group the group minimum is compared with the
+// running best and the group's first slot remembered (grp); the exact slot
+// is recovered by re-examining that one group (resolve), where the first
+// minimum wins as in a sequential scan.  Neighbour lists need no per-pair
+// test: a group holds a neighbour of i exactly when its minimum r^2 is below
+// h_i^2, and only such groups are re-examined.  Tiles that contain an
+// i-particle's own slot, and ragged tiles, take the per-pair path with
+// explicit self exclusion.
+template <int PREC, bool NBL>
+struct WideLanes {
+  using R = real_t<PREC>;
+  static constexpr int REC = rec4<PREC>();
+  IState<PREC> s0, s1;
+  int row0, row1, slot0, slot1;
+  bool v0, v1;
+  R h20, h21;
+  Totals t0, t1;
+  Sums<R> ts0, ts1; // tile sums
+  // nearest neighbour: fast-path best r^2 and its group; exact best
+  R gbest0, gbest1, ebest0, ebest1;
+  int grp0, grp1, eslot0, eslot1;
+
+  __device__ __forceinline__ void init(const ForceArgs &a, int r0, int r1, bool ok0, bool ok1) {
+    row0 = r0;
+    row1 = r1;
+    v0 = ok0;
+    v1 = ok1;
+    load_i<PREC>(s0, a, r0, ok0, slot0, h20);
+    load_i<PREC>(s1, a, r1, ok1, slot1, h21);
+    t0 = Totals{{0, 0, 0}, {0, 0, 0}, 0};
+    t1 = Totals{{0, 0, 0}, {0, 0, 0}, 0};
+    ts0.zero();
+    ts1.zero();
+    gbest0 = gbest1 = ebest0 = ebest1 = R(INFINITY);
+    grp0 = grp1 = eslot0 = eslot1 = -1;
+  }
+
+  // The cnt records of slots jbase .. jbase + cnt - 1 staged at tl.
+  __device__ __forceinline__ void tile(const float4 *__restrict__ tl, int jbase, int cnt, R eps2,
+                                       int *__restrict__ nb_count, int *__restrict__ nb_slot) {
+    const bool self_here =
+        (slot0 >= jbase && slot0 < jbase + cnt) || (slot1 >= jbase && slot1 < jbase + cnt);
+    if (cnt < kTile || __any(self_here)) {
+      MaskedRun<PREC, NBL> r0, r1;
+      r0.start();
+      r1.start();
+      int *c0 = nb_count + (v0 ? row0 : 0), *c1 = nb_count + (v1 ? row1 : 0);
+      int *l0 = nb_slot + static_cast<size_t>(v0 ? row0 : 0) * kNbMax;
+      int *l1 = nb_slot + static_cast<size_t>(v1 ? row1 : 0) * kNbMax;
+      for (int jj = 0; jj < cnt; ++jj) {
+        r0.step(s0, ts0, tl + jj * REC, jbase + jj, slot0, eps2, h20, ebest0, eslot0, c0, l0);
+        r1.step(s1, ts1, tl + jj * REC, jbase + jj, slot1, eps2, h21, ebest1, eslot1, c1, l1);
+      }
+      r0.finish(ts0);
+      r1.finish(ts1);
+    } else {
+      // bit k of nbm0 / nbm1: group k holds a neighbour of i0 / i1
+      unsigned nbm0 = 0u, nbm1 = 0u;
+#pragma unroll G6MI_GROUP_UNROLL
+      for (int g = 0; g < kTile; g += kGroup) {
+        R m0 = R(INFINITY), m1 = R(INFINITY);
+        if constexpr (PREC == G6MI_PREC_FP64) {
+#pragma unroll
+          for (int u = 0; u < kGroup; ++u) {
+            const float4 *rec = tl + (g + u) * REC;
+            m0 = fmin(m0, pair_core<PREC>(s0, ts0, rec, eps2));
+            m1 = fmin(m1, pair_core<PREC>(s1, ts1, rec, eps2));
+          }
+        } else {
+          Sums<R> g0, g1; // group sums, set by the group's first pair
+          m0 = pair_core<PREC, true>(s0, g0, tl + g * REC, eps2);
+          m1 = pair_core<PREC, true>(s1, g1, tl + g * REC, eps2);
+#pragma unroll
+          for (int u = 1; u < kGroup; ++u) {
+            const float4 *rec = tl + (g + u) * REC;
+            m0 = fmin(m0, pair_core<PREC>(s0, g0, rec, eps2));
+            m1 = fmin(m1, pair_core<PREC>(s1, g1, rec, eps2));
+          }
+          ts0.add(g0);
+          ts1.add(g1);
+        }
+        if (m0 < gbest0) {
+          gbest0 = m0;
+          grp0 = jbase + g;
+        }
+        if (m1 < gbest1) {
+          gbest1 = m1;
+          grp1 = jbase + g;
+        }
+        if constexpr (NBL) {
+          // the group minimum also tells whether any record is a neighbour
+          nbm0 |= (m0 < h20 ? 1u : 0u) << (g / kGroup);
+          nbm1 |= (m1 < h21 ? 1u : 0u) << (g / kGroup);
+        }
+      }
+      if constexpr (NBL) {
+        // rare: append the neighbours of the flagged groups
+        while (nbm0 | nbm1) {
+          const int k = __builtin_ctz(nbm0 | nbm1);
+          const unsigned bit = 1u << k;
+          for (int u = 0; u < kGroup; ++u) {
+            const int jj = k * kGroup + u;
+            const float4 *rec = tl + jj * REC;
+            if ((nbm0 & bit) && r2_of<PREC>(s0, rec) < h20) nb_append(nb_count, nb_slot, row0, jbase + jj);
+            if ((nbm1 & bit) && r2_of<PREC>(s1, rec) < h21) nb_append(nb_count, nb_slot, row1, jbase + jj);
+          }
+          nbm0 &= ~bit;
+          nbm1 &= ~bit;
+        }
+      }
+    }
+    fold(ts0, t0);
+    fold(ts1, t1);
+  }
+
+  // Resolve the pending groups from records at src (slot js at js - base).
+  __device__ __forceinline__ void resolve(const float4 *__restrict__ src, int base) {
+    resolve_group<PREC>(s0, grp0, 1, src, base, ebest0, eslot0);
+    resolve_group<PREC>(s1, grp1, 1, src, base, ebest1, eslot1);
+  }
+};
+
+// ------------------------------------- one i-particle on L lanes
+
+// Lane state of a narrow block: ipw i-particles per workgroup (a power of
+// two, at most kWG) and L = kWG / ipw lanes per i-particle.  Lane `sub` of an
+// i-particle handles records sub, sub + L, sub + 2L, ... of every tile
+// (Sec. 2.3, Fig. accMP1: spare threads split the j-range).  Full tiles
+// without an own slot use the grouped path of WideLanes with stride-L
+// groups.
+template <int PREC, bool NBL>
+struct NarrowLane {
+  using R = real_t<PREC>;
+  static constexpr int REC = rec4<PREC>();
+  IState<PREC> st;
+  int row, slot, sub, log2L, L, K;
+  bool valid;
+  R h2;
+  Totals t;
+  Sums<R> ts;
+  R gbest, ebest;
+  int grp, eslot;
+
+  __device__ __forceinline__ void init(const ForceArgs &a, int r, bool ok, int sub_, int log2L_) {
+    row = r;
+    valid = ok;
+    sub = sub_;
+    log2L = log2L_;
+    L = 1 << log2L_;
+    K = kTile >> log2L_; // records per lane in a full tile
+    load_i<PREC>(st, a, r, ok, slot, h2);
+    t = Totals{{0, 0, 0}, {0, 0, 0}, 0};
+    ts.zero();
+    gbest = ebest = R(INFINITY);
+    grp = eslot = -1;
+  }
+
+  __device__ __forceinline__ void tile(const float4 *__restrict__ tl, int jbase, int cnt, R eps2,
+                                       int *__restrict__ nb_count, int *__restrict__ nb_slot) {
+    const bool self_here = slot >= jbase && slot < jbase + cnt;
+    if (cnt < kTile || K < kGroup || __any(self_here)) {
+      int *nb_cnt = nb_count + (valid ? row : 0);
+      int *nb_row = nb_slot + static_cast<size_t>(valid ? row : 0) * kNbMax;
+      MaskedRun<PREC, NBL> run;
+      run.start();
+      for (int jj = sub; jj < cnt; jj += L)
+        run.step(st, ts, tl + jj * REC, jbase + jj, slot, eps2, h2, ebest, eslot, nb_cnt, nb_row);
+      run.finish(ts);
+    } else {
+      unsigned nbm = 0u;
+      for (int k0 = 0; k0 < K; k0 += kGroup) {
+        R m = R(INFINITY);
+        if constexpr (PREC == G6MI_PREC_FP64) {
+#pragma unroll
+          for (int u = 0; u < kGroup; ++u)
+            m = fmin(m, pair_core<PREC>(st, ts, tl + (sub + ((k0 + u) << log2L)) * REC, eps2));
+        } else {
+          Sums<R> gs; // group sums, set by the group's first pair
+          m = pair_core<PREC, true>(st, gs, tl + (sub + (k0 << log2L)) * REC, eps2);
+#pragma unroll
+          for (int u = 1; u < kGroup; ++u)
+            m = fmin(m, pair_core<PREC>(st, gs, tl + (sub + ((k0 + u) << log2L)) * REC, eps2));
+          ts.add(gs);
+        }
+        if (m < gbest) {
+          gbest = m;
+          grp = jbase + sub + (k0 << log2L);
+        }
+        if constexpr (NBL) nbm |= (m < h2 ? 1u : 0u) << (k0 / kGroup);
+      }
+      if constexpr (NBL) {
+        while (nbm) { // rare: append the neighbours of the flagged groups
+          const int g = __builtin_ctz(nbm);
+          nbm &= nbm - 1u;
+          for (int u = 0; u < kGroup; ++u) {
+            const int jj = sub + ((g * kGroup + u) << log2L);
+            if (r2_of<PREC>(st, tl + jj * REC) < h2) nb_append(nb_count, nb_slot, row, jbase + jj);
+          }
+        }
+      }
+    }
+    fold(ts, t);
+  }
+
+  __device__ __forceinline__ void resolve(const float4 *__restrict__ src, int base) {
+    resolve_group<PREC>(st, grp, L, src, base, ebest, eslot);
+  }
+
+  // Add the L lane totals of each i-particle in lane order through `red`
+  // (LDS, [9][kWG] doubles; the caller synchronises before reusing it).
+  // Afterwards the lanes with sub == 0 hold the i-particle's totals in t
+  // and its nearest-neighbour candidate in (bestd, bslot).
+  __device__ __forceinline__ void lane_sum(double *red, int tid, int il, int ipw, double &bestd,
+                                           int &bslot) {
+    bestd = static_cast<double>(ebest);
+    bslot = eslot;
+    if (L == 1) return;
+    __syncthreads();
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      red[d * kWG + tid] = t.acc[d];
+      red[(3 + d) * kWG + tid] = t.jrk[d];
+    }
+    red[6 * kWG + tid] = t.pot;
+    red[7 * kWG + tid] = bestd;
+    reinterpret_cast<int *>(red + 8 * kWG)[tid] = bslot;
+    __syncthreads();
+    if (sub == 0) {
+      for (int q = 1; q < L; ++q) {
+        const int o = q * ipw + il;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          t.acc[d] += red[d * kWG + o];
+          t.jrk[d] += red[(3 + d) * kWG + o];
+        }
+        t.pot += red[6 * kWG + o];
+        const double r2o = red[7 * kWG + o];
+        const int so = reinterpret_cast<const int *>(red + 8 * kWG)[o];
+        if (so >= 0 && (r2o < bestd || (r2o == bestd && (bslot < 0 || so < bslot)))) {
+          bestd = r2o;
+          bslot = so;
+        }
+      }
+    }
+  }
+};
+
+// LDS bytes of a narrow block: the tile, or the lane-sum area after it.
+template <int PREC> constexpr int narrow_lds_bytes() {
+  constexpr int red = kWG * 9 * 8; // 7 sums + r2 + slot per lane
+  constexpr int tile = kTile * rec4<PREC>() * 16;
+  return red > tile ? red : tile;
+}
+
+// Register budget: G6MI_WIDE_WAVES waves per SIMD for the float32
+// variants; float64 state takes twice the registers, so one wave fewer.
+template <int PREC> constexpr int wide_waves() {
+  return G6MI_WIDE_WAVES <= 1 ? 1 : (PREC == G6MI_PREC_FP64 ? G6MI_WIDE_WAVES - 1 : G6MI_WIDE_WAVES);
+}
+
+// ------------------------------------------------------------ finalisation
+
+// Final result of one i-particle from its nsplit j-split partials: the
+// float64 sum in split order, the lexicographic (r^2, slot) minimum of the
+// nearest-neighbour candidates, and the neighbour list turned from slots
+// into particle indices sorted ascending.  Component c of split s is at
+// part[s * sstride + c * cstride]; the candidates at nn_r2[s * nstride],
+// nn_slot[s * nstride] (pointers already at the i-particle).  Outputs go to
+// row `row`.  An overflowed list is queued in ovf_list (and its tag in
+// ovf_tag when given) for the exact pass, counted in
+// status[kStatusOverflowCount].  Returns the status flags of the row
+// (bit 0 non-finite output, bit 1 neighbour overflow).
+__device__ __forceinline__ int finish_row(int nsplit, const double *__restrict__ part, size_t sstride,
+                                          size_t cstride, const double *__restrict__ nn_r2,
+                                          const int *__restrict__ nn_slot, size_t nstride, int row,
+                                          const int *__restrict__ jindex,
+                                          const int *__restrict__ nb_count, int *__restrict__ nb_slot,
+                                          bool nbl, double *__restrict__ acc, double *__restrict__ jerk,
+                                          double *__restrict__ pot, int *__restrict__ nnb,
+                                          double *__restrict__ r2nn, int *__restrict__ status,
+                                          int *__restrict__ ovf_list, int *__restrict__ ovf_tag, int tag) {
+  double s[7] = {0, 0, 0, 0, 0, 0, 0};
+  double best = INFINITY;
+  int bslot = -1;
+  for (int q = 0; q < nsplit; ++q) {
+    const double *p = part + static_cast<size_t>(q) * sstride;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) s[c] += p[c * cstride];
+    const double r2 = nn_r2[q * nstride];
+    const int sl = nn_slot[q * nstride];
+    if (sl >= 0 && (r2 < best || (r2 == best && (bslot < 0 || sl < bslot)))) {
+      best = r2;
+      bslot = sl;
+    }
+  }
+  const size_t i = static_cast<size_t>(row);
+  bool finite = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    acc[3 * i + d] = s[d];
+    jerk[3 * i + d] = s[3 + d];
+    finite = finite && isfinite(s[d]) && isfinite(s[3 + d]);
+  }
+  pot[i] = -s[6];
+  finite = finite && isfinite(s[6]);
+  if (nnb) nnb[i] = bslot >= 0 ? jindex[bslot] : -1;
+  if (r2nn) r2nn[i] = bslot >= 0 ? best : INFINITY;
+  int fl = finite ? 0 : 1;
+  if (nbl) {
+    const int cnt = nb_count[i];
+    int *lst = nb_slot + i * kNbMax;
+    if (cnt > kNbMax) { // kept set decided later by the exact pass
+      fl |= 2;
+      const int q = atomicAdd(status + kStatusOverflowCount, 1);
+      ovf_list[q] = row;
+      if (ovf_tag) ovf_tag[q] = tag;
+      return fl;
+    }
+    for (int a = 0; a < cnt; ++a) lst[a] = jindex[lst[a]];
+    for (int a = 1; a < cnt; ++a) { // insertion sort: lists are short
+      const int key = lst[a];
+      int b = a - 1;
+      while (b >= 0 && lst[b] > key) {
+        lst[b + 1] = lst[b];
+        --b;
+      }
+      lst[b + 1] = key;
+    }
+  }
+  return fl;
+}
+
+// ---------------------------------------------- neighbour-list overflow
+
+// Rebuild the list of one overflowed i-particle as the kNbMax smallest
+// particle indices among its neighbours in slots jlo .. jhi - 1, ascending
+// (the oracle's convention).  Called by a whole workgroup.  The neighbour
+// test is the one of the interaction kernels (same separation and r^2
+// arithmetic on the same records, fetched by rec_of(js, scratch)).  A
+// binary search on the index threshold T counts the neighbours with index
+// below T (indices biased to unsigned order); then the kNbMax of them below
+// the final T are collected and rank-sorted.
+template <int PREC, class RecOf>
+__device__ void exact_list(const IState<PREC> &st, int slot, real_t<PREC> h2, int jlo, int jhi,
+                           const int *__restrict__ jindex, RecOf rec_of, int *__restrict__ lst,
+                           unsigned &s_cnt, int *s_keep) {
+  const int tid = threadIdx.x;
+  auto below = [&](unsigned long long T, bool collect) -> unsigned {
+    __syncthreads();
+    if (tid == 0) s_cnt = 0u;
+    __syncthreads();
+    unsigned c = 0u;
+    for (int js = jlo + tid; js < jhi; js += kWG) {
+      const unsigned key = static_cast<unsigned>(jindex[js]) ^ 0x80000000u;
+      float4 buf[4];
+      if (js != slot && key < T && r2_of<PREC>(st, rec_of(js, buf)) < h2) {
+        if (collect) {
+          const unsigned p = atomicAdd(&s_cnt, 1u);
+          if (p < static_cast<unsigned>(kNbMax)) s_keep[p] = jindex[js];
+        } else {
+          ++c;
+        }
+      }
+    }
+    if (!collect && c) atomicAdd(&s_cnt, c);
+    __syncthreads();
+    return s_cnt;
+  };
+  // smallest T with at least kNbMax neighbours below it
+  unsigned long long lo = 0ull, hi = 1ull << 32;
+  while (hi - lo > 1ull) {
+    const unsigned long long mid = (lo + hi) >> 1;
+    if (below(mid, false) >= static_cast<unsigned>(kNbMax)) hi = mid;
+    else lo = mid;
+  }
+  const unsigned got = below(hi, true);
+  const int n = got < static_cast<unsigned>(kNbMax) ? static_cast<int>(got) : kNbMax;
+  if (tid < n) { // rank sort; equal values ranked by position
+    const int v = s_keep[tid];
+    int r = 0;
+    for (int u = 0; u < n; ++u) r += (s_keep[u] < v) | ((s_keep[u] == v) & (u < tid));
+    lst[r] = v;
+  }
+  __syncthreads(); // s_keep is reused by the next i-particle
+}
+
+} // namespace g6mi

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "../../include/g6mi.h"
+
 #include <cstddef>
 #include <cstdint>
 
@@ -100,5 +102,62 @@ hipError_t launch_load(int nj, const double *t, const double *m,
                        const int *index, const double *x, const double *v,
                        const double *a2, const double *j6, const JMem &jm,
                        hipStream_t s);
+
+// ------------------------------------------ batched multi-cluster launch
+
+// Launch policy of a batch (see BatchPlan): item_work = work per item in
+// units of one tile x 512 i-particles, wide_min = smallest cluster block
+// that uses two i-particles per lane, max_split = cap on j-splits per
+// cluster (bounds the partial-sum buffer).
+struct BatchTune {
+  int item_work = 2;
+  int wide_min = 512;
+  int max_split = 64;
+};
+
+// Per-cluster plan written by the plan kernel: i-particles per workgroup
+// (512 = two per lane), j-splits and tiles per split, i-blocks, and the
+// cluster's first i-block counter, first work item and first partial entry.
+// Its work items are item0 .. item0 + nib * nsplit - 1, item item0 + r
+// being i-block r / nsplit, j-split r % nsplit.
+struct BatchPlan {
+  int ipw, log2ipw, nsplit, per, nib, ib0, item0, pad;
+  long long pbase;
+};
+
+// Work-queue state: next item, number of items (written by the plan kernel).
+struct BatchWork {
+  int head, nitems, nib, pad;
+};
+
+struct BatchArgs {
+  const g6mi_cluster *cl = nullptr; // [ncl] descriptors in device memory
+  BatchPlan *plan = nullptr;        // [ncl]
+  int *item_cl = nullptr;           // [item_cap] cluster of each work item
+  BatchWork *work = nullptr;
+  int ncl = 0, nj_set = 0, ni_total = 0, item_cap = 0;
+  BatchTune tune;
+  JMem jm;
+  ForceArgs fa;            // i-arrays over rows 0..ni_total-1; nb_count, nb_slot
+  double *part = nullptr;  // [7][pcap] split partials
+  double *nn_r2 = nullptr; // [pcap]
+  int *nn_slot = nullptr;  // [pcap]
+  size_t pcap = 0;
+  int *ibcnt = nullptr;    // [ni_total] finished splits per i-block
+  int nbl = 1;
+  double *acc = nullptr, *jerk = nullptr, *pot = nullptr, *r2nn = nullptr;
+  int *nnb = nullptr, *status = nullptr, *ovf_list = nullptr, *ovf_tag = nullptr;
+};
+
+// Rows cleared per workgroup of the plan launch besides workgroup 0.
+constexpr int kPlanZeroChunk = 4096;
+
+hipError_t launch_batch_plan(const BatchArgs &b, hipStream_t s);
+hipError_t launch_batch_force(int prec, const BatchArgs &b, int grid, hipStream_t s);
+hipError_t launch_batch_nb_exact(int prec, const BatchArgs &b, int novf, hipStream_t s);
+
+// Status flag of the batched launch: a cluster descriptor was out of range
+// or non-finite and its cluster was skipped.
+constexpr int kFlagBadCluster = 4;
 
 } // namespace g6mi

@@ -72,6 +72,27 @@ def test_header_constants_agree_with_binding(g6):
     assert int(consts["G6MI_NPIPES_DEFAULT"]) == g6.NPIPES_DEFAULT
     assert int(consts["G6MI_PREC_DS"]) == g6.PREC_DS
     assert int(consts["G6MI_EDEVICE"]) == g6.EDEVICE
+    assert int(consts["G6MI_MAX_HANDLES"]) == g6.MAX_HANDLES
+
+
+def _struct_fields(text, name):
+    body = re.search(r"typedef struct " + name + r" \{(.*?)\} " + name + ";", text, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    return re.findall(r"\b(int|double)\s+(\w+);", body)
+
+
+def test_batch_structs_match_header(g6):
+    """The binding's mirrors of g6mi_cluster and g6mi_batch_tuning have the
+    header's fields, in order, with the same sizes."""
+    text = open(HEADER).read()
+    cl = _struct_fields(text, "g6mi_cluster")
+    assert [n for _, n in cl] == list(g6.CLUSTER_DTYPE.names)
+    size = {"int": 4, "double": 8}
+    for (ty, n) in cl:
+        assert g6.CLUSTER_DTYPE[n].itemsize == size[ty]
+    assert sum(size[t] for t, _ in cl) == g6.CLUSTER_DTYPE.itemsize == 32
+    tu = _struct_fields(text, "g6mi_batch_tuning")
+    assert [n for _, n in tu] == [n for n, _ in g6.BatchTuning._fields_]
 
 
 def test_errors_not_aborts_without_gpu(g6):
@@ -92,7 +113,14 @@ def test_errors_not_aborts_without_gpu(g6):
     assert g6.g6_read_neighbour_list(0) == g6.ESTATE
     assert g6.g6mi_set_precision(0, "ds") == g6.ESTATE
     assert g6.g6_close(0) == g6.ESTATE
-    assert g6.g6_close(99) == g6.EINVAL
+    assert g6.g6_close(g6.MAX_HANDLES + 1) == g6.EINVAL
+    cl = g6.clusters([0], [1], [0], [1], [0.0], [0.0])
+    assert g6.g6mi_batch_calc(0, cl, 1, 1, 1, 1, 1, 1, 1, 1) == g6.ESTATE
+    assert g6.g6mi_batch_calc_device(0, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1) == g6.ESTATE
+    assert g6.g6mi_batch_use_graph(0, 1) == g6.ESTATE
+    assert g6.g6mi_batch_set_tuning(0, None) == g6.ESTATE
+    flags = np.zeros(1, dtype=np.int32)
+    assert g6._L().g6mi_last_status(0, g6._pi(flags)) == g6.ESTATE
 
 
 def test_fortran_aliases_take_addresses(g6):
