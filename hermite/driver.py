@@ -152,8 +152,11 @@ class BlockStepIntegrator:
         self._init()
 
     def _quantise(self, dt):
+        """Largest power of two at or below dt (clipped to [dt_min, dt_max]),
+        read exactly from the binary exponent: dt = f 2^e with f in [0.5, 1)."""
         dt = np.clip(dt, self.dt_min, self.dt_max)
-        return 2.0 ** np.floor(np.log2(dt))
+        _, e = np.frexp(dt)
+        return np.ldexp(1.0, e - 1)
 
     def _init(self):
         s = self.s

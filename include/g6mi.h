@@ -384,6 +384,51 @@ int g6mi_batch_autotune(int id, int ncl, const g6mi_cluster *cl,
                         g6mi_batch_tuning *best);
 
 
+/* ------------------------------------------- device-resident block steps
+ *
+ * The client side of Sec. 2.1 (i-prediction, Hermite corrector, block time
+ * steps) run on the GPU, so that a whole block step is one replayed graph
+ * of five kernels with no host round trip.  The particles are j-slots
+ * 0 .. n-1 of handle id: their t, mass, x, v and index as last set (all t
+ * equal); the integrator then owns those slots and updates them in place
+ * (position, velocity, a/2, jerk/6, time) after every step.
+ *
+ * Scheme (the 4th-order Hermite integrator with block steps that the
+ * paper's library serves, Sec. 2): block time t_b = min(t_k + dt_k); the
+ * particles with t_k + dt_k = t_b are predicted to t_b (Eq. (1)-(2) with
+ * their own a and jerk) and get new forces from the batched kernels with
+ * softening eps2 and neighbour radius^2 h2; the Makino-Aarseth corrector
+ * gives x, v at t_b; the next step is Aarseth's sqrt(eta (|a||a2| + |j|^2) /
+ * (|j||a3| + |a2|^2)) with a2 taken at the end of the step, halved while
+ * too long (down to dt_min) and doubled (up to dt_max) only when t_b is a
+ * multiple of the doubled step; the first step is eta_s |a| / |j| rounded
+ * down to a power of two in [dt_min, dt_max].
+ *
+ * g6mi_hermite_init computes the first forces and steps.  Returns 0, 1 if a
+ * force was not finite, or a negative code (G6MI_EINVAL: n larger than the
+ * slots set, unequal times, bad parameters).
+ *
+ * g6mi_hermite_advance performs block steps while the next block time is at
+ * most t_end, at most max_steps of them (blocks past t_end are not taken:
+ * with dt_max dividing t_end every particle ends exactly at t_end).  Writes
+ * the time of the last block taken to *t_reached and the running totals of
+ * block steps and particle steps since init to counts[0], counts[1] (either
+ * may be NULL).  Returns 0, 1 if a force was not finite, or a negative code
+ * (G6MI_ESTATE if not initialised or the j-memory was reallocated since).
+ *
+ * g6mi_hermite_state waits for the integrator and copies, for slots
+ * 0 .. n-1, position, velocity, acceleration, jerk, potential (from each
+ * particle's last force evaluation), time and step to the given host arrays
+ * (any may be NULL); it also refreshes the host copy of the j-memory.
+ * Returns 0 or a negative code. */
+int g6mi_hermite_init(int id, int n, double eps2, double h2, double eta,
+                      double eta_s, double dt_max, double dt_min);
+int g6mi_hermite_advance(int id, double t_end, long long max_steps,
+                         double *t_reached, long long counts[2]);
+int g6mi_hermite_state(int id, int n, double x[][3], double v[][3],
+                       double acc[][3], double jerk[][3], double pot[],
+                       double t[], double dt[]);
+
 /* ------------------------------------------------------ Fortran aliases */
 int g6_open_(const int *id);
 int g6_close_(const int *id);

@@ -89,6 +89,9 @@ _SIGS = {
     "g6mi_batch_get_tuning": (_i, [_i, ctypes.POINTER(BatchTuning)]),
     "g6mi_batch_autotune": (_i, [_i, _i, _V, _i, _V, _V, _V, _V, _V, _V, _V, _V, _V, _V, ctypes.c_char_p, _i,
                                  ctypes.POINTER(BatchTuning)]),
+    "g6mi_hermite_init": (_i, [_i, _i, _d, _d, _d, _d, _d, _d]),
+    "g6mi_hermite_advance": (_i, [_i, _d, ctypes.c_longlong, _D, ctypes.POINTER(ctypes.c_longlong)]),
+    "g6mi_hermite_state": (_i, [_i, _i, _D, _D, _D, _D, _D, _D, _D]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -387,6 +390,29 @@ def g6mi_batch_autotune(id, cl, ni_total, islot, xi, vi, h2, acc, jerk, pot, nnb
                                   _ptr(h2), _ptr(acc), _ptr(jerk), _ptr(pot), _ptr(nnb), _ptr(r2nn),
                                   _stream(stream), path, int(reps), ctypes.byref(t))
     return rc, t.as_dict()
+
+
+# ------------------------------------------------ device-resident block steps
+
+def g6mi_hermite_init(id, n, eps2, h2, eta, eta_s, dt_max, dt_min) -> int:
+    return _L().g6mi_hermite_init(id, int(n), float(eps2), float(h2), float(eta), float(eta_s), float(dt_max),
+                                  float(dt_min))
+
+
+def g6mi_hermite_advance(id, t_end, max_steps):
+    """Returns (rc, time reached, block steps, particle steps)."""
+    t = np.zeros(1)
+    cnt = (ctypes.c_longlong * 2)()
+    rc = _L().g6mi_hermite_advance(id, float(t_end), int(max_steps), _pd(t), cnt)
+    return rc, float(t[0]), int(cnt[0]), int(cnt[1])
+
+
+def g6mi_hermite_state(id, n):
+    """State of slots 0..n-1 as a dict of arrays (x, v, acc, jerk, pot, t, dt)."""
+    out = dict(x=np.zeros((n, 3)), v=np.zeros((n, 3)), acc=np.zeros((n, 3)), jerk=np.zeros((n, 3)),
+               pot=np.zeros(n), t=np.zeros(n), dt=np.zeros(n))
+    check(id, _L().g6mi_hermite_state(id, int(n), *(_pd(out[k]) for k in ("x", "v", "acc", "jerk", "pot", "t", "dt"))))
+    return out
 
 
 # --------------------------------------------------- convenience wrappers

@@ -150,6 +150,20 @@ struct Handle {
   std::vector<uint64_t> gkey;
   bool c_batch = false;    // the last calculation was a batch
   BatchArgs c_bargs;
+
+  // device-resident block steps
+  struct {
+    bool ready = false;
+    int n = 0;
+    HermiteArgs a;
+    double *jm_t = nullptr; // the j-memory the state lives in
+    size_t cap = 0;
+    DevBuf d_ctl, d_state, d_block;
+    PinBuf h_ctl;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint64_t> key;
+  } hs;
 };
 
 constexpr int kTimingRing = 4096;
@@ -590,14 +604,11 @@ int launch_batch_all(Handle &h, const BatchArgs &b, int grid, hipStream_t s, hip
   return 0;
 }
 
-// Enqueue a batch whose ncl descriptors are at d_cl (device memory).
-int enqueue_batch(Handle &h, int ncl, const g6mi_cluster *d_cl, int ni_total, const int *d_islot,
+// Work buffers and arguments of a batch (no launch).  nj_set bounds the
+// j-slots the descriptors may name.
+int prepare_batch(Handle &h, int ncl, const g6mi_cluster *d_cl, int ni_total, int nj_set, const int *d_islot,
                   const double *d_xi, const double *d_vi, const double *d_h2, double *d_acc,
-                  double *d_jerk, double *d_pot, int *d_nnb, double *d_r2nn, hipStream_t s) {
-  int rc = ensure_jmem(h, std::max<size_t>(1, h.n_contig));
-  if (rc) return rc;
-  rc = upload_dirty(h, s);
-  if (rc) return rc;
+                  double *d_jerk, double *d_pot, int *d_nnb, double *d_r2nn, BatchArgs &b) {
   const size_t n = static_cast<size_t>(std::max(ni_total, 1));
   BatchTune tune = h.btune;
   const size_t fit = kBatchPartialBudget / (n * kPartialEntryBytes);
@@ -617,13 +628,13 @@ int enqueue_batch(Handle &h, int ncl, const g6mi_cluster *d_cl, int ni_total, co
   HIPCHK(&h, ensure(h.d_flags, 64));
   HIPCHK(&h, ensure(h.d_ovf, 2 * n * sizeof(int)));
 
-  BatchArgs b;
+  b = BatchArgs{};
   b.cl = d_cl;
   b.plan = static_cast<BatchPlan *>(h.d_plan.p);
   b.item_cl = static_cast<int *>(h.d_items.p);
   b.work = static_cast<BatchWork *>(h.d_bwork.p);
   b.ncl = ncl;
-  b.nj_set = static_cast<int>(h.n_contig);
+  b.nj_set = nj_set;
   b.ni_total = ni_total;
   b.item_cap = static_cast<int>(item_cap);
   b.tune = tune;
@@ -649,6 +660,22 @@ int enqueue_batch(Handle &h, int ncl, const g6mi_cluster *d_cl, int ni_total, co
   b.status = static_cast<int *>(h.d_flags.p);
   b.ovf_list = static_cast<int *>(h.d_ovf.p);
   b.ovf_tag = b.ovf_list + n;
+  return 0;
+}
+
+// Enqueue a batch whose ncl descriptors are at d_cl (device memory).
+int enqueue_batch(Handle &h, int ncl, const g6mi_cluster *d_cl, int ni_total, const int *d_islot,
+                  const double *d_xi, const double *d_vi, const double *d_h2, double *d_acc,
+                  double *d_jerk, double *d_pot, int *d_nnb, double *d_r2nn, hipStream_t s) {
+  int rc = ensure_jmem(h, std::max<size_t>(1, h.n_contig));
+  if (rc) return rc;
+  rc = upload_dirty(h, s);
+  if (rc) return rc;
+  BatchArgs b;
+  rc = prepare_batch(h, ncl, d_cl, ni_total, static_cast<int>(h.n_contig), d_islot, d_xi, d_vi, d_h2, d_acc,
+                     d_jerk, d_pot, d_nnb, d_r2nn, b);
+  if (rc) return rc;
+  const BatchTune &tune = b.tune;
   const int grid = batch_grid(h, h.prec);
 
   h.shape[0] = 0;
@@ -780,6 +807,10 @@ G6MI_API int g6_close(int id) {
   (void)hipStreamSynchronize(h->stream);
   if (h->c_stream && h->c_stream != h->stream) (void)hipStreamSynchronize(h->c_stream);
   destroy_graph(*h);
+  if (h->hs.exec) (void)hipGraphExecDestroy(h->hs.exec);
+  if (h->hs.graph) (void)hipGraphDestroy(h->hs.graph);
+  for (DevBuf *b : {&h->hs.d_ctl, &h->hs.d_state, &h->hs.d_block}) b->release();
+  h->hs.h_ctl.release();
   for (DevBuf *b : {&h->d_jm, &h->d_pred, &h->d_stage, &h->d_i, &h->d_out, &h->d_part,
                     &h->d_nnr2, &h->d_nnslot, &h->d_nbcount, &h->d_nblist, &h->d_flags,
                     &h->d_ovf, &h->d_cl, &h->d_plan, &h->d_items, &h->d_bwork, &h->d_ibcnt})
@@ -1401,6 +1432,237 @@ G6MI_API int g6mi_batch_autotune(int id, int ncl, const g6mi_cluster *cl, int ni
     std::fprintf(f, "%s %s %d %d %d %d %.6f\n", kTuneTag, key.c_str(), win.item_work, win.wide_min,
                  win.wg_per_cu, win.max_split, win_ms);
     std::fclose(f);
+  }
+  return G6MI_OK;
+}
+
+// ------------------------------------------------ device-resident block steps
+
+namespace {
+void hs_destroy_graph(Handle &h) {
+  if (h.hs.exec) (void)hipGraphExecDestroy(h.hs.exec);
+  if (h.hs.graph) (void)hipGraphDestroy(h.hs.graph);
+  h.hs.exec = nullptr;
+  h.hs.graph = nullptr;
+  h.hs.key.clear();
+}
+
+// Batch arguments of the current block (descriptor in the control block).
+int hs_batch(Handle &h, BatchArgs &b) {
+  HermiteArgs &a = h.hs.a;
+  const int n = h.hs.n;
+  int *nnb = reinterpret_cast<int *>(a.pot1 + 2 * static_cast<size_t>(n));
+  return prepare_batch(h, 1, &a.ctl->desc, n, n, a.active, a.xi, a.vi, a.h2i, a.acc1, a.jrk1, a.pot1, nnb,
+                       a.pot1 + n, b);
+}
+
+int hs_read_ctl(Handle &h, hipStream_t s, HermiteCtl &c) {
+  HIPCHK(&h, hipMemcpyAsync(h.hs.h_ctl.p, h.hs.a.ctl, sizeof(HermiteCtl), hipMemcpyDeviceToHost, s));
+  HIPCHK(&h, hipStreamSynchronize(s));
+  std::memcpy(&c, h.hs.h_ctl.p, sizeof(HermiteCtl));
+  return 0;
+}
+} // namespace
+
+G6MI_API int g6mi_hermite_init(int id, int n, double eps2, double h2, double eta, double eta_s, double dt_max,
+                               double dt_min) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  if (h->pending) return fail(h, G6MI_ESTATE, "a host-path calculation is pending");
+  if (n < 1 || static_cast<size_t>(n) > h->n_contig)
+    return fail(h, G6MI_EINVAL, "n must be 1 .. the number of j-slots set from slot 0");
+  if (!std::isfinite(eps2) || eps2 < 0.0 || !std::isfinite(h2) || !(eta > 0.0) || !std::isfinite(eta) ||
+      !(eta_s > 0.0) || !std::isfinite(eta_s) || !(dt_min > 0.0) || !(dt_max >= dt_min) || !std::isfinite(dt_max))
+    return fail(h, G6MI_EINVAL, "bad integrator parameters");
+  const double t0 = h->h_rec[0];
+  for (int k = 1; k < n; ++k)
+    if (h->h_rec[static_cast<size_t>(k) * kRecDoubles] != t0)
+      return fail(h, G6MI_EINVAL, "the particles must share one time to start");
+  HIPCHK(h, hipSetDevice(h->device));
+  hipStream_t s = h->stream;
+  int rc = ensure_jmem(*h, std::max<size_t>(1, h->n_contig));
+  if (!rc) rc = upload_dirty(*h, s);
+  if (rc) return rc;
+  auto &hs = h->hs;
+  hs_destroy_graph(*h);
+  hs.ready = false;
+  const size_t cap = h->jm.cap, nn = static_cast<size_t>(n);
+  HIPCHK(h, ensure(hs.d_ctl, sizeof(HermiteCtl)));
+  HIPCHK(h, ensure(hs.d_state, 8 * cap * sizeof(double)));
+  // block: xi, vi, acc1, jrk1 [n][3]; h2i, pot1, r2nn [n]; nnb, active [n] int
+  HIPCHK(h, ensure(hs.d_block, (15 * nn) * sizeof(double) + 2 * nn * sizeof(int)));
+  HIPCHK(h, ensure(hs.h_ctl, sizeof(HermiteCtl)));
+  HermiteArgs &a = hs.a;
+  a = HermiteArgs{};
+  a.ctl = static_cast<HermiteCtl *>(hs.d_ctl.p);
+  a.jm = h->jm;
+  double *st = static_cast<double *>(hs.d_state.p);
+  a.acc = st;
+  a.jrk = st + 3 * cap;
+  a.dt = st + 6 * cap;
+  a.pot = st + 7 * cap;
+  a.n = n;
+  double *blk = static_cast<double *>(hs.d_block.p);
+  a.xi = blk;
+  a.vi = blk + 3 * nn;
+  a.acc1 = blk + 6 * nn;
+  a.jrk1 = blk + 9 * nn;
+  a.h2i = blk + 12 * nn;
+  a.pot1 = blk + 13 * nn; // then r2nn [n] and nnb, active (ints)
+  a.active = reinterpret_cast<int *>(blk + 15 * nn) + nn;
+  a.eps2 = eps2;
+  a.h2 = h2;
+  a.eta = eta;
+  a.eta_s = eta_s;
+  a.dt_max = dt_max;
+  a.dt_min = dt_min;
+  hs.n = n;
+  hs.cap = cap;
+  hs.jm_t = h->jm.t;
+  HermiteCtl c{};
+  c.tnext_key = 0xfff0000000000000ull;
+  c.t_end = INFINITY;
+  c.time = t0;
+  c.desc = g6mi_cluster{0, n, 0, 0, t0, eps2};
+  std::memcpy(hs.h_ctl.p, &c, sizeof(c));
+  HIPCHK(h, hipMemcpyAsync(a.ctl, hs.h_ctl.p, sizeof(c), hipMemcpyHostToDevice, s));
+  HIPCHK(h, launch_hs_reset(a, s));
+  HIPCHK(h, launch_hs_select(a, s));
+  BatchArgs b;
+  rc = hs_batch(*h, b);
+  if (rc) return rc;
+  HIPCHK(h, launch_batch_plan(b, s));
+  HIPCHK(h, launch_batch_force(h->prec, b, batch_grid(*h, h->prec), s));
+  HIPCHK(h, launch_hs_correct(a, true, s));
+  rc = hs_read_ctl(*h, s, c);
+  if (rc) return rc;
+  h->c_have = false; // the work buffers now hold the integrator's block
+  hs.ready = true;
+  return (c.flags & 1) ? G6MI_WARN : G6MI_OK;
+}
+
+G6MI_API int g6mi_hermite_advance(int id, double t_end, long long max_steps, double *t_reached,
+                                  long long counts[2]) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  auto &hs = h->hs;
+  if (!hs.ready) return fail(h, G6MI_ESTATE, "g6mi_hermite_init was not called");
+  if (h->pending) return fail(h, G6MI_ESTATE, "a host-path calculation is pending");
+  if (h->jm.t != hs.jm_t || h->jm.cap != hs.cap)
+    return fail(h, G6MI_ESTATE, "the j-memory was reallocated since g6mi_hermite_init");
+  if (!std::isfinite(t_end) || max_steps < 0) return fail(h, G6MI_EINVAL, "bad t_end or max_steps");
+  HIPCHK(h, hipSetDevice(h->device));
+  hipStream_t s = h->stream;
+  int rc = upload_dirty(*h, s);
+  if (rc) return rc;
+  HermiteArgs &a = hs.a;
+  HermiteCtl c;
+  std::memcpy(hs.h_ctl.p, &t_end, sizeof(double));
+  HIPCHK(h, hipMemcpyAsync(&a.ctl->t_end, hs.h_ctl.p, sizeof(double), hipMemcpyHostToDevice, s));
+  BatchArgs b;
+  rc = hs_batch(*h, b);
+  if (rc) return rc;
+  const int grid = batch_grid(*h, h->prec);
+  std::vector<uint64_t> key = graph_key(*h, b, grid, s);
+  if (!hs.exec || key != hs.key) {
+    hs_destroy_graph(*h);
+    HIPCHK(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t e = launch_hs_select(a, s);
+    if (e == hipSuccess) e = launch_batch_plan(b, s);
+    if (e == hipSuccess) e = launch_batch_force(h->prec, b, grid, s);
+    if (e == hipSuccess) e = launch_hs_correct(a, false, s);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &g);
+    if (e == hipSuccess) e = ec;
+    if (e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return hip_fail(h, e, "block-step graph capture");
+    }
+    hs.graph = g;
+    e = hipGraphInstantiate(&hs.exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      hs.exec = nullptr;
+      hs_destroy_graph(*h);
+      return hip_fail(h, e, "hipGraphInstantiate");
+    }
+    hs.key = std::move(key);
+  }
+  // Replays past the last block before t_end select nothing and change
+  // nothing, so steps are launched in chunks between checks.
+  long long launched = 0;
+  bool done = false;
+  while (launched < max_steps && !done) {
+    const long long chunk = std::min<long long>(32, max_steps - launched);
+    for (long long q = 0; q < chunk; ++q) HIPCHK(h, hipGraphLaunch(hs.exec, s));
+    launched += chunk;
+    rc = hs_read_ctl(*h, s, c);
+    if (rc) return rc;
+    done = c.done != 0;
+  }
+  if (launched == 0) {
+    rc = hs_read_ctl(*h, s, c);
+    if (rc) return rc;
+  }
+  if (t_reached) *t_reached = c.time;
+  if (counts) {
+    counts[0] = c.block_steps;
+    counts[1] = c.particle_steps;
+  }
+  h->c_have = false;
+  return (c.flags & 1) ? G6MI_WARN : G6MI_OK;
+}
+
+G6MI_API int g6mi_hermite_state(int id, int n, double x[][3], double v[][3], double acc[][3],
+                                double jerk[][3], double pot[], double t[], double dt[]) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  auto &hs = h->hs;
+  if (!hs.ready) return fail(h, G6MI_ESTATE, "g6mi_hermite_init was not called");
+  if (n < 0 || n > hs.n) return fail(h, G6MI_EINVAL, "n exceeds the integrated particles");
+  if (h->jm.t != hs.jm_t || h->jm.cap != hs.cap)
+    return fail(h, G6MI_ESTATE, "the j-memory was reallocated since g6mi_hermite_init");
+  HIPCHK(h, hipSetDevice(h->device));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (n == 0) return G6MI_OK;
+  const HermiteArgs &a = hs.a;
+  const size_t cap = hs.cap, nn = static_cast<size_t>(n);
+  std::vector<double> col(nn);
+  auto get = [&](const double *src) -> int {
+    HIPCHK(h, hipMemcpy(col.data(), src, nn * sizeof(double), hipMemcpyDeviceToHost));
+    return 0;
+  };
+  // vectors: component d of slot k at [d * cap + k]; also refresh the host
+  // master copy of the j-memory (x, v, a/2, jerk/6, t)
+  struct Vec {
+    const double *src;
+    double (*out)[3];
+    int rec;    // offset of the vector in the staged record
+    double div; // the record holds value / div (a/2, jerk/6)
+  } vecs[4] = {{a.jm.x, x, 2, 1.0}, {a.jm.v, v, 5, 1.0}, {a.acc, acc, 8, 2.0}, {a.jrk, jerk, 11, 6.0}};
+  for (const Vec &q : vecs)
+    for (int d = 0; d < 3; ++d) {
+      int rc = get(q.src + d * cap);
+      if (rc) return rc;
+      for (size_t k = 0; k < nn; ++k) {
+        if (q.out) q.out[k][d] = col[k];
+        h->h_rec[k * kRecDoubles + q.rec + d] = col[k] / q.div;
+      }
+    }
+  int rc = get(a.jm.t);
+  if (rc) return rc;
+  for (size_t k = 0; k < nn; ++k) {
+    if (t) t[k] = col[k];
+    h->h_rec[k * kRecDoubles] = col[k];
+  }
+  if (pot) {
+    rc = get(a.pot);
+    if (rc) return rc;
+    std::copy(col.begin(), col.end(), pot);
+  }
+  if (dt) {
+    rc = get(a.dt);
+    if (rc) return rc;
+    std::copy(col.begin(), col.end(), dt);
   }
   return G6MI_OK;
 }

@@ -1,0 +1,276 @@
+// Device-resident block steps of the 4th-order Hermite integrator (the
+// client side of the paper's CPU/GPU split, Sec. 2 and 2.1, moved onto the
+// GPU): one block step is
+//
+//   hs_min_kernel      next block time t_b = min_k (t_k + dt_k)
+//   hs_select_kernel   the particles with t_k + dt_k = t_b, predicted to t_b
+//                      in float64 (Eq. (1)-(2) with the particle's own
+//                      a and jerk); the last workgroup writes the one-cluster
+//                      descriptor that the batched force launch reads
+//   batch_plan_kernel, batch_kernel   forces on the block (g6mi_batch.hip)
+//   hs_correct_kernel  Hermite corrector, Aarseth time step, power-of-two
+//                      block quantisation; the corrected particle is written
+//                      back into the j-memory (its a/2 and jerk/6 too)
+//
+// Every launch has a fixed grid and reads the block size from device
+// memory, so a whole step is one captured graph, replayed without the host.
+// The integrator's formulas follow the host driver (hermite/driver.py) term
+// by term, with float contraction switched off so that both round alike.
+
+#include "g6mi_device.h"
+
+namespace g6mi {
+
+// Order-preserving map of doubles onto unsigned 64-bit keys, so that the
+// minimum over a grid is one atomicMin.
+__device__ __forceinline__ unsigned long long order_key(double x) {
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(x));
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double key_value(unsigned long long k) {
+  const unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+  return __longlong_as_double(static_cast<long long>(b));
+}
+constexpr unsigned long long kKeyInf = 0xfff0000000000000ull; // order_key(+inf)
+
+__global__ __launch_bounds__(256) void hs_min_kernel(HermiteArgs h) {
+  __shared__ double s_min[256];
+  const int tid = threadIdx.x;
+  const int k = blockIdx.x * 256 + tid;
+  s_min[tid] = k < h.n ? h.jm.t[k] + h.dt[k] : INFINITY;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) s_min[tid] = fmin(s_min[tid], s_min[tid + off]);
+    __syncthreads();
+  }
+  if (tid == 0) {
+    atomicMin(&h.ctl->tnext_key, order_key(s_min[0]));
+    if (blockIdx.x == 0) h.ctl->ni_count = 0;
+  }
+}
+
+// Taylor prediction of particle k to time tb from its own a and jerk, the
+// host driver's expression: x + tau (v + tau (a/2 + tau j/6)).
+__device__ __forceinline__ void predict_particle(const HermiteArgs &h, int k, double tb, double *xp,
+                                                 double *vp) {
+#pragma clang fp contract(off)
+  const double tau = tb - h.jm.t[k];
+  for (int d = 0; d < 3; ++d) {
+    const size_t e = d * h.jm.cap + k;
+    const double a2 = 0.5 * h.acc[e];
+    const double j6 = h.jrk[e] / 6.0;
+    xp[d] = h.jm.x[e] + tau * (h.jm.v[e] + tau * (a2 + tau * j6));
+    vp[d] = h.jm.v[e] + tau * (2.0 * a2 + tau * (3.0 * j6));
+  }
+}
+
+__global__ __launch_bounds__(256) void hs_select_kernel(HermiteArgs h) {
+  __shared__ int s_wave[4], s_base, s_last;
+  const int tid = threadIdx.x;
+  const int k = blockIdx.x * 256 + tid;
+  HermiteCtl *ctl = h.ctl;
+  const double tb = key_value(ctl->tnext_key);
+  const bool go = tb <= ctl->t_end;
+  const bool act = go && k < h.n && h.jm.t[k] + h.dt[k] == tb;
+  // slots of this block's active particles: wave counts, one atomic per block
+  const unsigned long long m = __ballot(act);
+  const int lane = tid & 63, wave = tid >> 6;
+  if (lane == 0) s_wave[wave] = __popcll(m);
+  __syncthreads();
+  if (tid == 0) {
+    const int tot = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    s_base = tot ? atomicAdd(&ctl->ni_count, tot) : 0;
+  }
+  __syncthreads();
+  if (act) {
+    int q = s_base + __popcll(m & ((1ull << lane) - 1ull));
+    for (int w = 0; w < wave; ++w) q += s_wave[w];
+    double xp[3], vp[3];
+    predict_particle(h, k, tb, xp, vp);
+    h.active[q] = k;
+    for (int d = 0; d < 3; ++d) {
+      h.xi[3 * static_cast<size_t>(q) + d] = xp[d];
+      h.vi[3 * static_cast<size_t>(q) + d] = vp[d];
+    }
+    h.h2i[q] = h.h2;
+  }
+  // the last workgroup to finish publishes the block as a descriptor
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_last = atomicAdd(&ctl->blocks_done, 1) == static_cast<int>(gridDim.x) - 1;
+  __syncthreads();
+  if (s_last && tid == 0) {
+    __threadfence();
+    g6mi_cluster d;
+    d.joff = 0;
+    d.nj = h.n;
+    d.ioff = 0;
+    d.ni = go ? ctl->ni_count : 0;
+    d.ti = go ? tb : ctl->time;
+    d.eps2 = h.eps2;
+    ctl->desc = d;
+    ctl->blocks_done = 0;
+    ctl->done = go ? 0 : 1;
+  }
+}
+
+__device__ __forceinline__ double norm3(const double *a) {
+#pragma clang fp contract(off)
+  return sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+}
+
+// Power-of-two step at or below dt, within [dt_min, dt_max]: 2^floor(log2)
+// taken exactly from the binary exponent.
+__device__ __forceinline__ double quantise(double dt, double dt_min, double dt_max) {
+  dt = fmin(fmax(dt, dt_min), dt_max);
+  int e;
+  (void)frexp(dt, &e); // dt = f 2^e, f in [0.5, 1)
+  return ldexp(1.0, e - 1);
+}
+
+// Corrector (Makino & Aarseth 1992) for the block's particles, then the
+// Aarseth criterion with the second derivative at the end of the step, and
+// the block rule: halve while too long, double only when the time is a
+// multiple of the doubled step.
+__global__ __launch_bounds__(256) void hs_correct_kernel(HermiteArgs h) {
+#pragma clang fp contract(off)
+  HermiteCtl *ctl = h.ctl;
+  const int ni = ctl->desc.ni;
+  const double tb = ctl->desc.ti;
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->tnext_key = kKeyInf;
+    if (ni > 0) {
+      ctl->block_steps += 1;
+      ctl->particle_steps += ni;
+      ctl->time = tb;
+    }
+  }
+  if (q >= ni) return;
+  const int k = h.active[q];
+  const size_t cap = h.jm.cap;
+  const double dt = tb - h.jm.t[k];
+  double a0[3], j0[3], a1[3], j1[3], a2[3], a3[3], a2e[3];
+  bool finite = true;
+  for (int d = 0; d < 3; ++d) {
+    a0[d] = h.acc[d * cap + k];
+    j0[d] = h.jrk[d * cap + k];
+    a1[d] = h.acc1[3 * static_cast<size_t>(q) + d];
+    j1[d] = h.jrk1[3 * static_cast<size_t>(q) + d];
+    finite = finite && isfinite(a1[d]) && isfinite(j1[d]);
+  }
+  const double dt2 = dt * dt, dt3 = dt2 * dt, dt4 = dt3 * dt, dt5 = dt4 * dt;
+  for (int d = 0; d < 3; ++d) {
+    a2[d] = (-6.0 * (a0[d] - a1[d]) - dt * (4.0 * j0[d] + 2.0 * j1[d])) / dt2;
+    a3[d] = (12.0 * (a0[d] - a1[d]) + 6.0 * dt * (j0[d] + j1[d])) / dt3;
+  }
+  double xp[3], vp[3];
+  for (int d = 0; d < 3; ++d) {
+    xp[d] = h.xi[3 * static_cast<size_t>(q) + d];
+    vp[d] = h.vi[3 * static_cast<size_t>(q) + d];
+  }
+  for (int d = 0; d < 3; ++d) {
+    const double x1 = xp[d] + a2[d] * dt4 / 24.0 + a3[d] * dt5 / 120.0;
+    const double v1 = vp[d] + a2[d] * dt3 / 6.0 + a3[d] * dt4 / 24.0;
+    a2e[d] = a2[d] + dt * a3[d];
+    h.jm.x[d * cap + k] = x1;
+    h.jm.v[d * cap + k] = v1;
+    h.acc[d * cap + k] = a1[d];
+    h.jrk[d * cap + k] = j1[d];
+    h.jm.a2[d * cap + k] = a1[d] / 2.0;
+    h.jm.j6[d * cap + k] = j1[d] / 6.0;
+  }
+  const double na1 = norm3(a1), nj1 = norm3(j1), na3 = norm3(a3), na2e = norm3(a2e);
+  const double num = na1 * na2e + nj1 * nj1;
+  const double den = nj1 * na3 + na2e * na2e;
+  const double dt_new = sqrt(h.eta * num / fmax(den, 1e-300));
+  const double old = h.dt[k];
+  double nw = old;
+  if (dt_new < nw) {
+    do {
+      nw *= 0.5;
+    } while (dt_new < nw && nw > h.dt_min);
+  }
+  if (dt_new >= 2.0 * old && fmod(tb, 2.0 * old) == 0.0 && 2.0 * old <= h.dt_max) nw = 2.0 * old;
+  h.jm.t[k] = tb;
+  h.dt[k] = nw;
+  h.pot[k] = h.pot1[q];
+  if (!finite) atomicOr(&ctl->flags, 1);
+}
+
+// First force evaluation of every particle at the common start time: a,
+// jerk and potential stored, first step eta_s |a| / |jerk| quantised.
+__global__ __launch_bounds__(256) void hs_start_kernel(HermiteArgs h) {
+#pragma clang fp contract(off)
+  HermiteCtl *ctl = h.ctl;
+  const int ni = ctl->desc.ni;
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->tnext_key = kKeyInf;
+    ctl->time = ctl->desc.ti;
+  }
+  if (q >= ni) return;
+  const int k = h.active[q];
+  const size_t cap = h.jm.cap;
+  double a1[3], j1[3];
+  bool finite = true;
+  for (int d = 0; d < 3; ++d) {
+    a1[d] = h.acc1[3 * static_cast<size_t>(q) + d];
+    j1[d] = h.jrk1[3 * static_cast<size_t>(q) + d];
+    finite = finite && isfinite(a1[d]) && isfinite(j1[d]);
+    h.acc[d * cap + k] = a1[d];
+    h.jrk[d * cap + k] = j1[d];
+    h.jm.a2[d * cap + k] = a1[d] / 2.0;
+    h.jm.j6[d * cap + k] = j1[d] / 6.0;
+  }
+  const double dt = h.eta_s * norm3(a1) / fmax(norm3(j1), 1e-300);
+  h.dt[k] = quantise(dt, h.dt_min, h.dt_max);
+  h.pot[k] = h.pot1[q];
+  if (!finite) atomicOr(&ctl->flags, 1);
+}
+
+// Clear the step state before the first force evaluation: every particle
+// due at its own (common) time, a and jerk zero as in the host driver.
+__global__ __launch_bounds__(256) void hs_reset_kernel(HermiteArgs h) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    h.ctl->tnext_key = kKeyInf;
+    h.ctl->blocks_done = 0;
+    h.ctl->flags = 0;
+    h.ctl->done = 0;
+    h.ctl->block_steps = 0;
+    h.ctl->particle_steps = 0;
+  }
+  if (k >= h.n) return;
+  const size_t cap = h.jm.cap;
+  h.dt[k] = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    h.acc[d * cap + k] = 0.0;
+    h.jrk[d * cap + k] = 0.0;
+    h.jm.a2[d * cap + k] = 0.0;
+    h.jm.j6[d * cap + k] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+static inline dim3 grid_n(int n) { return dim3(static_cast<unsigned>((n > 0 ? n : 1) + 255) / 256); }
+
+hipError_t launch_hs_reset(const HermiteArgs &h, hipStream_t s) {
+  hipLaunchKernelGGL(hs_reset_kernel, grid_n(h.n), dim3(256), 0, s, h);
+  return hipGetLastError();
+}
+hipError_t launch_hs_select(const HermiteArgs &h, hipStream_t s) {
+  hipLaunchKernelGGL(hs_min_kernel, grid_n(h.n), dim3(256), 0, s, h);
+  hipLaunchKernelGGL(hs_select_kernel, grid_n(h.n), dim3(256), 0, s, h);
+  return hipGetLastError();
+}
+hipError_t launch_hs_correct(const HermiteArgs &h, bool start, hipStream_t s) {
+  if (start)
+    hipLaunchKernelGGL(hs_start_kernel, grid_n(h.n), dim3(256), 0, s, h);
+  else
+    hipLaunchKernelGGL(hs_correct_kernel, grid_n(h.n), dim3(256), 0, s, h);
+  return hipGetLastError();
+}
+
+} // namespace g6mi

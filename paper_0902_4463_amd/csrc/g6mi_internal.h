@@ -16,10 +16,10 @@ namespace g6mi {
 #define G6MI_TILE 256 // j-records staged in LDS per tile
 #endif
 #ifndef G6MI_GROUP
-#define G6MI_GROUP 8 // j-records per nearest-neighbour group
+#define G6MI_GROUP 16 // j-records per nearest-neighbour group
 #endif
 #ifndef G6MI_GROUP_UNROLL
-#define G6MI_GROUP_UNROLL 2 // groups per unrolled loop body
+#define G6MI_GROUP_UNROLL 1 // groups per unrolled loop body
 #endif
 #ifndef G6MI_WIDE_WAVES
 #define G6MI_WIDE_WAVES 3 // register budget of the wide kernel: waves per SIMD (0: free)
@@ -159,5 +159,41 @@ hipError_t launch_batch_nb_exact(int prec, const BatchArgs &b, int novf, hipStre
 // Status flag of the batched launch: a cluster descriptor was out of range
 // or non-finite and its cluster was skipped.
 constexpr int kFlagBadCluster = 4;
+
+// ------------------------------------------ device-resident block steps
+
+// Control block of the device-resident Hermite integrator (device memory).
+struct HermiteCtl {
+  unsigned long long tnext_key; // order key of the next block time (+inf between steps)
+  int ni_count;                 // particles selected so far in this step
+  int blocks_done;              // finished workgroups of the select launch
+  int done;                     // 1: no particle is due at or before t_end
+  int flags;                    // bit 0: a non-finite force
+  long long block_steps, particle_steps;
+  double t_end;                 // run limit, set by the host
+  double time;                  // time of the last completed block step
+  g6mi_cluster desc;            // the current block as a one-cluster batch
+};
+
+// The integrator state is the j-memory (slots 0..n-1: t, m, x, v, a/2,
+// jerk/6, index) plus a and jerk themselves, the step and the potential.
+struct HermiteArgs {
+  HermiteCtl *ctl = nullptr;
+  JMem jm;
+  double *acc = nullptr, *jrk = nullptr;  // [3][cap] at each particle's own time
+  double *dt = nullptr, *pot = nullptr;   // [cap]
+  int n = 0;
+  int *active = nullptr;                  // [n] slots of the block, in selection order
+  double *xi = nullptr, *vi = nullptr;    // [n][3] block predicted to the block time
+  double *h2i = nullptr;                  // [n]
+  double *acc1 = nullptr, *jrk1 = nullptr, *pot1 = nullptr; // [n][3], [n][3], [n] new forces
+  double eps2 = 0, h2 = 0, eta = 0, eta_s = 0, dt_max = 0, dt_min = 0;
+};
+
+hipError_t launch_hs_reset(const HermiteArgs &h, hipStream_t s);
+// next block time and the block itself (two launches)
+hipError_t launch_hs_select(const HermiteArgs &h, hipStream_t s);
+// corrector and new steps (start = the first evaluation: store and pick steps)
+hipError_t launch_hs_correct(const HermiteArgs &h, bool start, hipStream_t s);
 
 } // namespace g6mi
