@@ -34,8 +34,8 @@ PEAK_FP32_TFLOPS = 157.3    # MI355X vector FP32 (dense)
 PEAK_FP64_TFLOPS = 78.6     # MI355X vector FP64
 METRIC = "pair interactions/s & Gflop/s (60 flop/pair) at N=2^20, DS vs FP64 at stated err"
 KERNEL_SOURCES = ("paper_0902_4463_amd/csrc/g6mi_kernels.hip", "paper_0902_4463_amd/csrc/g6mi_device.h",
-                  "paper_0902_4463_amd/csrc/g6mi_internal.h")
-TRAFFIC_PROFILE = "profiles/force_wide_ds_plummer_N1048576_traffic.md"
+                  "paper_0902_4463_amd/csrc/g6mi_internal.h", "paper_0902_4463_amd/csrc/g6mi_spatial.hip")
+TRAFFIC_PROFILE = "profiles/force_spatial_ds_plummer_N1048576_traffic.md"
 
 
 def kernel_source_hash() -> str:
@@ -290,12 +290,14 @@ def main():
     peak = PEAK_FP64_TFLOPS if args.variant == "fp64" else PEAK_FP32_TFLOPS
     default_run = (args.variant == "ds" and n == 2 ** 20 and ni == n and not args.shape
                    and not args.no_neighbour_lists)
+    # the library orders large double-single blocks spatially (g6mi_set_spatial)
+    spatial_run = args.variant == "ds" and ni >= 4096 and n >= 512 and not args.shape
     traffic = profiled_traffic() if default_run else None
     roofline = dict(bound="alu", achieved=round(force_tflops, 3), peak=peak, unit="TFLOP/s",
                     frac=round(force_tflops / peak, 4), traffic=traffic,
                     traffic_source=TRAFFIC_PROFILE if traffic else None,
-                    kernel=("force_wide" if main_run["shape"]["i_per_group"] == 512 else "force_kernel")
-                    + f"<{args.variant}>", flop_per_pair=FLOP_PER_PAIR,
+                    kernel=("force_spatial" if spatial_run else "force_wide" if main_run["shape"]["i_per_group"] == 512
+                            else "force_kernel") + f"<{args.variant}>", flop_per_pair=FLOP_PER_PAIR,
                     pairs_per_launch=pairs, avg_launch_ms=round(main_run["force_ms"], 4))
 
     variants = {}

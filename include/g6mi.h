@@ -224,6 +224,22 @@ int g6mi_get_precision(int id);
  * computed.  Returns 0 or a negative code. */
 int g6mi_set_neighbour_lists(int id, int on);
 
+/* Spatial ordering of double-single calculations: 0 off, 1 (default) for
+ * blocks of at least 4096 i-particles against at least 512 j-slots, 2 for
+ * every double-single calculation.  With the ordering on, the j-records and
+ * the i-block are sorted along a Morton curve of their positions, so that
+ * each tile of 256 j-records and each workgroup's 512 i-particles is
+ * compact; tiles farther from the i-particles than their own radius use
+ * float32 separations of coordinates relative to the tile centre (within
+ * four float32 roundings of the separation, against two for Eq. (3)), the
+ * other tiles the double-single separation.  Results stay within the same
+ * tolerances; nearest-neighbour ties between different records may resolve
+ * differently.  In mode 1 a launch-shape override (g6mi_set_shape with
+ * i_per_group > 0) turns the ordering off; in mode 2 the ordering uses 512
+ * i-particles per workgroup whatever the override.  Returns 0, G6MI_EINVAL
+ * or G6MI_ESTATE. */
+int g6mi_set_spatial(int id, int mode);
+
 /* Override the launch shape of the interaction kernel: i-particles per
  * workgroup (a power of two, 1..512; 512 means two i-particles per lane,
  * 256 or fewer one per lane or several lanes per i-particle) and number of

@@ -74,6 +74,7 @@ _SIGS = {
     "g6mi_get_precision": (_i, [_i]),
     "g6mi_set_neighbour_lists": (_i, [_i, _i]),
     "g6mi_set_shape": (_i, [_i, _i, _i]),
+    "g6mi_set_spatial": (_i, [_i, _i]),
     "g6mi_get_shape": (_i, [_i, _I]),
     "g6mi_enable_timing": (_i, [_i, _i]),
     "g6mi_last_timing": (_i, [_i, _D]),
@@ -274,6 +275,11 @@ def g6mi_get_precision(id) -> int:
 
 def g6mi_set_neighbour_lists(id, on) -> int:
     return _L().g6mi_set_neighbour_lists(id, int(bool(on)))
+
+
+def g6mi_set_spatial(id, mode) -> int:
+    """0 off, 1 large double-single blocks (default), 2 every double-single calculation."""
+    return _L().g6mi_set_spatial(id, int(mode))
 
 
 def g6mi_set_shape(id, i_per_group, j_splits) -> int:

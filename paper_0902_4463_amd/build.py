@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libg6mi.so")
 SOURCES = [os.path.join(CSRC, "g6mi_kernels.hip"), os.path.join(CSRC, "g6mi_batch.hip"),
-           os.path.join(CSRC, "g6mi_hermite.hip"),
+           os.path.join(CSRC, "g6mi_hermite.hip"), os.path.join(CSRC, "g6mi_spatial.hip"),
            os.path.join(CSRC, "g6mi_api.cpp")]
 ARCH = "gfx950"
 

@@ -86,6 +86,7 @@ struct Handle {
   std::string arch;
   int prec = G6MI_PREC_DS;
   bool nbl = true;
+  int spatial = 1; // 0 off, 1 for large DS blocks, 2 always (DS)
   int user_ipw = 0, user_nsplit = 0;
   int shape[4] = {0, 0, 0, 0};
   std::string err;
@@ -112,6 +113,8 @@ struct Handle {
 
   // work buffers
   DevBuf d_part, d_nnr2, d_nnslot, d_nbcount, d_nblist, d_flags, d_ovf;
+  DevBuf d_sp; // spatial ordering: one allocation cut into SpatialBufs
+  SpatialBufs sp;
 
   // calculation state
   bool pending = false;
@@ -311,9 +314,20 @@ int ilog2(int v) {
 constexpr int kWaveTarget = G6MI_WG_PER_CU;
 constexpr int kMinTiles = 8;
 
+// Spatial ordering (g6mi_spatial.hip) for double-single blocks of at least
+// this many i-particles against at least two tiles (automatic mode).
+constexpr int kSpatialMinNi = 4096;
+
+bool use_spatial(const Handle &h, int ni, int nj) {
+  if (h.prec != G6MI_PREC_DS || ni <= 0 || nj <= 0) return false;
+  if (h.spatial == 2) return true;
+  return h.spatial == 1 && !h.user_ipw && ni >= kSpatialMinNi && nj >= 2 * kTile;
+}
+
 void choose_shape(Handle &h, int ni, int nj, int &ipw, int &nsplit) {
   const int ntiles = (nj + kTile - 1) / kTile;
-  if (h.user_ipw) ipw = h.user_ipw;
+  if (use_spatial(h, ni, nj)) ipw = 2 * kWG;
+  else if (h.user_ipw) ipw = h.user_ipw;
   else if (ni >= 2 * kWG) ipw = 2 * kWG; // two i-particles per lane
   else {
     ipw = kWG;
@@ -330,6 +344,39 @@ void choose_shape(Handle &h, int ni, int nj, int &ipw, int &nsplit) {
     nsplit = std::max(1, std::min(nsplit, std::max(1, ntiles / kMinTiles)));
   }
   nsplit = std::min(nsplit, 4096);
+}
+
+// Buffers of the spatial ordering for nj records and ni i-particles.
+int ensure_spatial(Handle &h, int nj, int ni) {
+  const size_t n = static_cast<size_t>(std::max(nj, ni)), j = static_cast<size_t>(nj), i = static_cast<size_t>(ni);
+  const size_t ntiles = (j + kTile - 1) / kTile;
+  size_t temp = 0;
+  HIPCHK(&h, spatial_sort_bytes(static_cast<int>(n), &temp));
+  auto al = [](size_t b) { return round_up(std::max<size_t>(b, 1), 256); };
+  const size_t sizes[] = {al(6 * sizeof(unsigned)), al(n * 4), al(n * 4), al(n * 4), al(j * 4), al(i * 4),
+                          al(j * 4), al(j * 48), al(ntiles * 64), al(temp)};
+  size_t total = 0;
+  for (size_t b : sizes) total += b;
+  HIPCHK(&h, ensure(h.d_sp, total));
+  char *p = static_cast<char *>(h.d_sp.p);
+  void *parts[10];
+  for (int k = 0; k < 10; ++k) {
+    parts[k] = p;
+    p += sizes[k];
+  }
+  SpatialBufs &b = h.sp;
+  b.box = static_cast<unsigned *>(parts[0]);
+  b.keys_in = static_cast<unsigned *>(parts[1]);
+  b.keys_out = static_cast<unsigned *>(parts[2]);
+  b.vals_in = static_cast<int *>(parts[3]);
+  b.jperm = static_cast<int *>(parts[4]);
+  b.iperm = static_cast<int *>(parts[5]);
+  b.inv = static_cast<int *>(parts[6]);
+  b.sorted = static_cast<float4 *>(parts[7]);
+  b.tinfo = static_cast<float4 *>(parts[8]);
+  b.temp = parts[9];
+  b.temp_bytes = sizes[9];
+  return 0;
 }
 
 int enqueue_calc(Handle &h, int nj, int ni, const int *d_islot, const double *d_xi,
@@ -363,9 +410,15 @@ int enqueue_calc(Handle &h, int nj, int ni, const int *d_islot, const double *d_
     }
     ev = h.evs[h.n_timed].data();
   }
+  const bool spatial = use_spatial(h, ni, nj);
+  if (spatial) {
+    int rc2 = ensure_spatial(h, nj, ni);
+    if (rc2) return rc2;
+  }
   if (ev) HIPCHK(&h, hipEventRecord(ev[0], s));
   HIPCHK(&h, launch_predict(h.prec, nj, h.ti, h.jm, h.d_pred.p,
                             static_cast<int *>(h.d_nbcount.p), ni, status, s));
+  if (spatial) HIPCHK(&h, launch_spatial_prep(h.sp, nj, ni, h.d_pred.p, d_xi, s));
   if (ev) HIPCHK(&h, hipEventRecord(ev[1], s));
   ForceArgs a;
   a.jpred = h.d_pred.p;
@@ -383,7 +436,13 @@ int enqueue_calc(Handle &h, int nj, int ni, const int *d_islot, const double *d_
   a.nn_slot = static_cast<int *>(h.d_nnslot.p);
   a.nb_count = static_cast<int *>(h.d_nbcount.p);
   a.nb_slot = static_cast<int *>(h.d_nblist.p);
-  HIPCHK(&h, launch_force(h.prec, h.nbl, a, nsplit, s));
+  if (spatial) {
+    ForceArgs as = a;
+    as.jpred = h.sp.sorted;
+    HIPCHK(&h, launch_force_spatial(h.nbl, as, h.sp, nsplit, s));
+  } else {
+    HIPCHK(&h, launch_force(h.prec, h.nbl, a, nsplit, s));
+  }
   if (ev) HIPCHK(&h, hipEventRecord(ev[2], s));
   HIPCHK(&h, launch_reduce(nsplit, ni, a.part, a.nn_r2, a.nn_slot, h.jm.index, a.nb_count,
                            a.nb_slot, h.nbl, d_acc, d_jerk, d_pot, d_nnb, d_r2nn, status,
@@ -813,7 +872,7 @@ G6MI_API int g6_close(int id) {
   h->hs.h_ctl.release();
   for (DevBuf *b : {&h->d_jm, &h->d_pred, &h->d_stage, &h->d_i, &h->d_out, &h->d_part,
                     &h->d_nnr2, &h->d_nnslot, &h->d_nbcount, &h->d_nblist, &h->d_flags,
-                    &h->d_ovf, &h->d_cl, &h->d_plan, &h->d_items, &h->d_bwork, &h->d_ibcnt})
+                    &h->d_ovf, &h->d_cl, &h->d_plan, &h->d_items, &h->d_bwork, &h->d_ibcnt, &h->d_sp})
     b->release();
   for (PinBuf *b : {&h->h_stage, &h->h_i, &h->h_out, &h->h_cl}) b->release();
   if (h->cl_ev) (void)hipEventDestroy(h->cl_ev);
@@ -1040,6 +1099,14 @@ G6MI_API int g6mi_set_neighbour_lists(int id, int on) {
   Handle *h = get_open(id);
   if (!h) return code_for_missing(id);
   h->nbl = on != 0;
+  return G6MI_OK;
+}
+
+G6MI_API int g6mi_set_spatial(int id, int mode) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  if (mode < 0 || mode > 2) return fail(h, G6MI_EINVAL, "spatial mode must be 0, 1 or 2");
+  h->spatial = mode;
   return G6MI_OK;
 }
 

@@ -354,11 +354,16 @@ __device__ __forceinline__ void nb_append(int *__restrict__ nb_count, int *__res
   if (pos < kNbMax) nb_slot[static_cast<size_t>(row) * kNbMax + pos] = jslot;
 }
 
+// j-slot of a record in the spatially sorted order (held in its second
+// float4's w component; the first three floats are DS lo or velocity).
+__device__ __forceinline__ int rec_slot(const float4 *rec) { return __float_as_int(rec[1].w); }
+
 // Exact slot of a grouped-path nearest neighbour: re-examine the kGroup
-// records of the group starting at slot grp (records grp, grp + stride, ...)
-// and merge the lexicographic (r^2, slot) minimum into (best, bslot).  The
-// record of slot js is at src + (js - base) records.  Clears grp.
-template <int PREC>
+// records of the group starting at position grp (positions grp, grp +
+// stride, ...) and merge the lexicographic (r^2, slot) minimum into (best,
+// bslot).  The record at position js is at src + (js - base) records; its
+// slot is js, or (SORTED) the slot stored in the record.  Clears grp.
+template <int PREC, bool SORTED = false>
 __device__ __forceinline__ void resolve_group(const IState<PREC> &st, int &grp, int stride,
                                               const float4 *__restrict__ src, int base,
                                               real_t<PREC> &best, int &bslot) {
@@ -366,10 +371,12 @@ __device__ __forceinline__ void resolve_group(const IState<PREC> &st, int &grp, 
   if (grp < 0) return;
   for (int u = 0; u < kGroup; ++u) {
     const int js = grp + u * stride;
-    const real_t<PREC> r = r2_of<PREC>(st, src + static_cast<size_t>(js - base) * REC);
-    if (r < best || (r == best && js < bslot)) {
+    const float4 *rec = src + static_cast<size_t>(js - base) * REC;
+    const real_t<PREC> r = r2_of<PREC>(st, rec);
+    const int sl = SORTED ? rec_slot(rec) : js;
+    if (r < best || (r == best && sl < bslot)) {
       best = r;
-      bslot = js;
+      bslot = sl;
     }
   }
   grp = -1;
@@ -390,12 +397,18 @@ __device__ __forceinline__ void resolve_group(const IState<PREC> &st, int &grp, 
 // h_i^2, and only such groups are re-examined.  Tiles that contain an
 // i-particle's own slot, and ragged tiles, take the per-pair path with
 // explicit self exclusion.
-template <int PREC, bool NBL>
+//
+// SORTED: the j-records are in a spatial order (positions are not slots):
+// own-tile detection uses the own record's position (pos0, pos1, set by the
+// caller), and the slots of neighbours and nearest neighbours are read from
+// the records.  tile_far walks a far tile in float32 coordinates relative to
+// the tile's centre (see force_spatial).
+template <int PREC, bool NBL, bool SORTED = false>
 struct WideLanes {
   using R = real_t<PREC>;
   static constexpr int REC = rec4<PREC>();
   IState<PREC> s0, s1;
-  int row0, row1, slot0, slot1;
+  int row0, row1, slot0, slot1, pos0, pos1;
   bool v0, v1;
   R h20, h21;
   Totals t0, t1;
@@ -411,6 +424,8 @@ struct WideLanes {
     v1 = ok1;
     load_i<PREC>(s0, a, r0, ok0, slot0, h20);
     load_i<PREC>(s1, a, r1, ok1, slot1, h21);
+    pos0 = slot0;
+    pos1 = slot1;
     t0 = Totals{{0, 0, 0}, {0, 0, 0}, 0};
     t1 = Totals{{0, 0, 0}, {0, 0, 0}, 0};
     ts0.zero();
@@ -419,11 +434,17 @@ struct WideLanes {
     grp0 = grp1 = eslot0 = eslot1 = -1;
   }
 
-  // The cnt records of slots jbase .. jbase + cnt - 1 staged at tl.
+  // slot of the record at position jbase + jj, staged at tl
+  __device__ __forceinline__ int jslot_at(const float4 *__restrict__ tl, int jbase, int jj) const {
+    if constexpr (SORTED) return rec_slot(tl + jj * REC);
+    else return jbase + jj;
+  }
+
+  // The cnt records at positions jbase .. jbase + cnt - 1 staged at tl.
   __device__ __forceinline__ void tile(const float4 *__restrict__ tl, int jbase, int cnt, R eps2,
                                        int *__restrict__ nb_count, int *__restrict__ nb_slot) {
     const bool self_here =
-        (slot0 >= jbase && slot0 < jbase + cnt) || (slot1 >= jbase && slot1 < jbase + cnt);
+        (pos0 >= jbase && pos0 < jbase + cnt) || (pos1 >= jbase && pos1 < jbase + cnt);
     if (cnt < kTile || __any(self_here)) {
       MaskedRun<PREC, NBL> r0, r1;
       r0.start();
@@ -432,8 +453,9 @@ struct WideLanes {
       int *l0 = nb_slot + static_cast<size_t>(v0 ? row0 : 0) * kNbMax;
       int *l1 = nb_slot + static_cast<size_t>(v1 ? row1 : 0) * kNbMax;
       for (int jj = 0; jj < cnt; ++jj) {
-        r0.step(s0, ts0, tl + jj * REC, jbase + jj, slot0, eps2, h20, ebest0, eslot0, c0, l0);
-        r1.step(s1, ts1, tl + jj * REC, jbase + jj, slot1, eps2, h21, ebest1, eslot1, c1, l1);
+        const int js = jslot_at(tl, jbase, jj);
+        r0.step(s0, ts0, tl + jj * REC, js, slot0, eps2, h20, ebest0, eslot0, c0, l0);
+        r1.step(s1, ts1, tl + jj * REC, js, slot1, eps2, h21, ebest1, eslot1, c1, l1);
       }
       r0.finish(ts0);
       r1.finish(ts1);
@@ -485,8 +507,8 @@ struct WideLanes {
           for (int u = 0; u < kGroup; ++u) {
             const int jj = k * kGroup + u;
             const float4 *rec = tl + jj * REC;
-            if ((nbm0 & bit) && r2_of<PREC>(s0, rec) < h20) nb_append(nb_count, nb_slot, row0, jbase + jj);
-            if ((nbm1 & bit) && r2_of<PREC>(s1, rec) < h21) nb_append(nb_count, nb_slot, row1, jbase + jj);
+            if ((nbm0 & bit) && r2_of<PREC>(s0, rec) < h20) nb_append(nb_count, nb_slot, row0, jslot_at(tl, jbase, jj));
+            if ((nbm1 & bit) && r2_of<PREC>(s1, rec) < h21) nb_append(nb_count, nb_slot, row1, jslot_at(tl, jbase, jj));
           }
           nbm0 &= ~bit;
           nbm1 &= ~bit;
@@ -497,10 +519,64 @@ struct WideLanes {
     fold(ts1, t1);
   }
 
-  // Resolve the pending groups from records at src (slot js at js - base).
+  // Resolve the pending groups from records at src (position js at js - base).
   __device__ __forceinline__ void resolve(const float4 *__restrict__ src, int base) {
-    resolve_group<PREC>(s0, grp0, 1, src, base, ebest0, eslot0);
-    resolve_group<PREC>(s1, grp1, 1, src, base, ebest1, eslot1);
+    resolve_group<PREC, SORTED>(s0, grp0, 1, src, base, ebest0, eslot0);
+    resolve_group<PREC, SORTED>(s1, grp1, 1, src, base, ebest1, eslot1);
+  }
+
+  // A full far tile in float32 records relative to the tile's centre
+  // (float4{x - c, m}, float4{v, slot}) with the i-particles' positions
+  // relative to the same centre in f0, f1 (their velocities as in s0, s1):
+  // the grouped path of `tile` with a three-operation separation.  Nearest-
+  // neighbour groups are kept by position, as on the DS path.
+  __device__ __forceinline__ void tile_far(const float4 *__restrict__ ftl, int jbase, R eps2,
+                                           const IState<G6MI_PREC_FP32> &f0, const IState<G6MI_PREC_FP32> &f1,
+                                           int *__restrict__ nb_count, int *__restrict__ nb_slot) {
+    static_assert(PREC == G6MI_PREC_DS, "the far path refines the double-single variant");
+    constexpr int FREC = rec4<G6MI_PREC_FP32>();
+    unsigned nbm0 = 0u, nbm1 = 0u;
+#pragma unroll G6MI_GROUP_UNROLL
+    for (int g = 0; g < kTile; g += kGroup) {
+      Sums<R> g0, g1;
+      R m0 = pair_core<G6MI_PREC_FP32, true>(f0, g0, ftl + g * FREC, eps2);
+      R m1 = pair_core<G6MI_PREC_FP32, true>(f1, g1, ftl + g * FREC, eps2);
+#pragma unroll
+      for (int u = 1; u < kGroup; ++u) {
+        const float4 *rec = ftl + (g + u) * FREC;
+        m0 = fmin(m0, pair_core<G6MI_PREC_FP32>(f0, g0, rec, eps2));
+        m1 = fmin(m1, pair_core<G6MI_PREC_FP32>(f1, g1, rec, eps2));
+      }
+      ts0.add(g0);
+      ts1.add(g1);
+      if (m0 < gbest0) {
+        gbest0 = m0;
+        grp0 = jbase + g;
+      }
+      if (m1 < gbest1) {
+        gbest1 = m1;
+        grp1 = jbase + g;
+      }
+      if constexpr (NBL) {
+        nbm0 |= (m0 < h20 ? 1u : 0u) << (g / kGroup);
+        nbm1 |= (m1 < h21 ? 1u : 0u) << (g / kGroup);
+      }
+    }
+    if constexpr (NBL) {
+      while (nbm0 | nbm1) {
+        const int k = __builtin_ctz(nbm0 | nbm1);
+        const unsigned bit = 1u << k;
+        for (int u = 0; u < kGroup; ++u) {
+          const float4 *rec = ftl + (k * kGroup + u) * FREC;
+          if ((nbm0 & bit) && r2_of<G6MI_PREC_FP32>(f0, rec) < h20) nb_append(nb_count, nb_slot, row0, rec_slot(rec));
+          if ((nbm1 & bit) && r2_of<G6MI_PREC_FP32>(f1, rec) < h21) nb_append(nb_count, nb_slot, row1, rec_slot(rec));
+        }
+        nbm0 &= ~bit;
+        nbm1 &= ~bit;
+      }
+    }
+    fold(ts0, t0);
+    fold(ts1, t1);
   }
 };
 

@@ -21,6 +21,9 @@ namespace g6mi {
 #ifndef G6MI_GROUP_UNROLL
 #define G6MI_GROUP_UNROLL 1 // groups per unrolled loop body
 #endif
+#ifndef G6MI_FAR_K
+#define G6MI_FAR_K 2.0f // far tile: gap to the i-box at least this many tile radii
+#endif
 #ifndef G6MI_WIDE_WAVES
 #define G6MI_WIDE_WAVES 3 // register budget of the wide kernel: waves per SIMD (0: free)
 #endif
@@ -102,6 +105,36 @@ hipError_t launch_load(int nj, const double *t, const double *m,
                        const int *index, const double *x, const double *v,
                        const double *a2, const double *j6, const JMem &jm,
                        hipStream_t s);
+
+// ------------------------------------------ spatially ordered DS blocks
+
+// Device buffers of the spatial ordering (g6mi_spatial.hip).
+struct SpatialBufs {
+  unsigned *box = nullptr;                       // [6] j box as order keys
+  unsigned *keys_in = nullptr, *keys_out = nullptr; // [max(nj, ni)]
+  int *vals_in = nullptr;                        // [max(nj, ni)]
+  int *jperm = nullptr;                          // [nj] slot at each sorted position
+  int *iperm = nullptr;                          // [ni] i-row at each sorted position
+  int *inv = nullptr;                            // [nj] sorted position of each slot
+  float4 *sorted = nullptr;                      // [nj][3] DS records in sorted order
+  float4 *tinfo = nullptr;                       // [ntiles][4] centre, radius, box
+  void *temp = nullptr;                          // radix-sort scratch
+  size_t temp_bytes = 0;
+};
+
+struct SpatialArgs {
+  const int *iperm = nullptr;
+  const int *inv = nullptr;
+  const float4 *tinfo = nullptr;
+};
+
+// Scratch bytes of a radix sort of n (key, index) pairs.
+hipError_t spatial_sort_bytes(int n, size_t *bytes);
+// Box, keys, sorts of j and i, sorted records and tile table.
+hipError_t launch_spatial_prep(const SpatialBufs &b, int nj, int ni, const void *jpred, const double *xi,
+                               hipStream_t s);
+// The DS interaction over sorted records (a.jpred = b.sorted); i-blocks of 512.
+hipError_t launch_force_spatial(bool nbl, const ForceArgs &a, const SpatialBufs &b, int nsplit, hipStream_t s);
 
 // ------------------------------------------ batched multi-cluster launch
 

@@ -1,0 +1,370 @@
+// Spatially ordered evaluation of large double-single blocks.
+//
+// The double-single separation of Eq. (3) costs nine float32 operations per
+// pair against three for a plain float32 difference, and it is needed only
+// where a float32 difference would lose the digits: between particles close
+// compared with their distance from the origin of the coordinates.  Here the
+// j-records and the i-block are put in a space-filling (Morton) order, so
+// that a tile of 256 consecutive records and a workgroup's 512 i-particles
+// each occupy a compact box.  For a tile whose box is farther from the
+// i-box than K times the tile's own radius r_t, both sides are re-expressed
+// relative to the tile's centre c (a double-single difference per record and
+// per i-particle, once per tile) and the pairs use float32 differences of
+// those small coordinates.  With |x_j - c| <= r_t <= |x_j - x_i| / K the
+// separation error stays below 2 (1 + 1/K) units of the float32 rounding
+// (the double-single form's is below 2); nearer tiles, tiles holding an
+// i-particle's own record and ragged tiles take the double-single path.
+//
+//   sp_init_kernel, sp_bbox_kernel    bounding box of the predicted j (hi parts)
+//   sp_jkeys_kernel, sp_ikeys_kernel  30-bit Morton keys of j and i positions
+//   (rocPRIM radix sort of (key, index) pairs)
+//   sp_gather_kernel                  records in sorted order, slot in the
+//                                     second float4's w; position of each slot
+//   sp_tile_kernel                    per tile: centre (double-single),
+//                                     radius, box
+//   force_spatial<NBL>                the wide interaction kernel over the
+//                                     sorted records and i-blocks
+
+#include <cstring>
+
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include "g6mi_device.h"
+
+namespace g6mi {
+
+// Order-preserving keys of floats for atomic min / max.
+__device__ __forceinline__ unsigned fkey(float x) {
+  const unsigned b = __float_as_uint(x);
+  return (b >> 31) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float fkey_value(unsigned k) {
+  return __uint_as_float((k >> 31) ? (k & 0x7fffffffu) : ~k);
+}
+
+__global__ __launch_bounds__(64) void sp_init_kernel(unsigned *__restrict__ box) {
+  const int t = threadIdx.x;
+  if (t < 3) box[t] = 0xffffffffu; // min keys
+  else if (t < 6) box[t] = 0u;     // max keys
+}
+
+// Workgroup minimum / maximum of six floats held by every thread, combined
+// into box[] with one atomic each (thread 0).
+__device__ __forceinline__ void box_reduce(float lo[3], float hi[3], unsigned *__restrict__ box) {
+  __shared__ float s[6][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = fminf(lo[d], __shfl_xor(lo[d], off));
+      hi[d] = fmaxf(hi[d], __shfl_xor(hi[d], off));
+    }
+  if (lane == 0)
+    for (int d = 0; d < 3; ++d) {
+      s[d][wave] = lo[d];
+      s[3 + d][wave] = hi[d];
+    }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int d = threadIdx.x;
+    atomicMin(box + d, fkey(fminf(fminf(s[d][0], s[d][1]), fminf(s[d][2], s[d][3]))));
+    atomicMax(box + 3 + d, fkey(fmaxf(fmaxf(s[3 + d][0], s[3 + d][1]), fmaxf(s[3 + d][2], s[3 + d][3]))));
+  }
+}
+
+__global__ __launch_bounds__(256) void sp_bbox_kernel(int nj, const float4 *__restrict__ rec,
+                                                      unsigned *__restrict__ box) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  if (k < nj) {
+    const float4 p = rec[3 * static_cast<size_t>(k)];
+    lo[0] = hi[0] = p.x;
+    lo[1] = hi[1] = p.y;
+    lo[2] = hi[2] = p.z;
+  }
+  box_reduce(lo, hi, box);
+}
+
+// 10 bits per axis, interleaved (x lowest).
+__device__ __forceinline__ unsigned spread10(unsigned v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000ffu;
+  v = (v | (v << 8)) & 0x0300f00fu;
+  v = (v | (v << 4)) & 0x030c30c3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+__device__ __forceinline__ unsigned morton(float x, float y, float z, const unsigned *__restrict__ box) {
+  const float p[3] = {x, y, z};
+  unsigned key = 0u;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float lo = fkey_value(box[d]), hi = fkey_value(box[3 + d]);
+    const float span = hi - lo;
+    float q = span > 0.0f ? (p[d] - lo) * (1024.0f / span) : 0.0f;
+    q = fminf(fmaxf(q, 0.0f), 1023.0f); // also catches NaN (fmax/fmin drop it)
+    key |= spread10(static_cast<unsigned>(q)) << d;
+  }
+  return key;
+}
+
+__global__ __launch_bounds__(256) void sp_jkeys_kernel(int nj, const float4 *__restrict__ rec,
+                                                       const unsigned *__restrict__ box,
+                                                       unsigned *__restrict__ keys, int *__restrict__ vals) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= nj) return;
+  const float4 p = rec[3 * static_cast<size_t>(k)];
+  keys[k] = morton(p.x, p.y, p.z, box);
+  vals[k] = k;
+}
+
+__global__ __launch_bounds__(256) void sp_ikeys_kernel(int ni, const double *__restrict__ xi,
+                                                       const unsigned *__restrict__ box,
+                                                       unsigned *__restrict__ keys, int *__restrict__ vals) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= ni) return;
+  const double *x = xi + 3 * static_cast<size_t>(i);
+  keys[i] = morton(static_cast<float>(x[0]), static_cast<float>(x[1]), static_cast<float>(x[2]), box);
+  vals[i] = i;
+}
+
+// Record at sorted position p = record of slot perm[p], the slot stored in
+// the w of its second float4; inv[slot] = position.
+__global__ __launch_bounds__(256) void sp_gather_kernel(int nj, const int *__restrict__ perm,
+                                                        const float4 *__restrict__ src,
+                                                        float4 *__restrict__ dst, int *__restrict__ inv) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= nj) return;
+  const int k = perm[p];
+  const size_t s = 3 * static_cast<size_t>(k), d = 3 * static_cast<size_t>(p);
+  float4 lo = src[s + 1];
+  lo.w = __int_as_float(k);
+  dst[d] = src[s];
+  dst[d + 1] = lo;
+  dst[d + 2] = src[s + 2];
+  inv[k] = p;
+}
+
+// One workgroup per tile of sorted records: box of the hi parts, centre c
+// (float64 midpoint, split double-single), radius r_t = the largest
+// |(x_hi - c_hi) + (x_lo - c_lo)| computed as on the far path, rounded up.
+// tinfo[4 t .. 4 t + 3] = {c_hi, r_t}, {c_lo, 0}, {box min, 0}, {box max, 0}.
+__global__ __launch_bounds__(256) void sp_tile_kernel(int nj, const float4 *__restrict__ rec,
+                                                      float4 *__restrict__ tinfo) {
+  __shared__ unsigned s_box[6];
+  __shared__ float s_c[6];
+  __shared__ float s_r[4];
+  const int tid = threadIdx.x;
+  const int k = blockIdx.x * kTile + tid;
+  const bool ok = k < nj;
+  if (tid < 6) s_box[tid] = tid < 3 ? 0xffffffffu : 0u;
+  __syncthreads();
+  float4 ph = make_float4(0, 0, 0, 0), pl = ph;
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  if (ok) {
+    ph = rec[3 * static_cast<size_t>(k)];
+    pl = rec[3 * static_cast<size_t>(k) + 1];
+    lo[0] = hi[0] = ph.x;
+    lo[1] = hi[1] = ph.y;
+    lo[2] = hi[2] = ph.z;
+  }
+  box_reduce(lo, hi, s_box);
+  __syncthreads();
+  if (tid < 3) {
+    const double c = 0.5 * (static_cast<double>(fkey_value(s_box[tid])) + static_cast<double>(fkey_value(s_box[3 + tid])));
+    const float chi = static_cast<float>(c);
+    s_c[tid] = chi;
+    s_c[3 + tid] = static_cast<float>(c - static_cast<double>(chi));
+  }
+  __syncthreads();
+  float r = 0.0f;
+  if (ok) {
+    const float dx = (ph.x - s_c[0]) + (pl.x - s_c[3]);
+    const float dy = (ph.y - s_c[1]) + (pl.y - s_c[4]);
+    const float dz = (ph.z - s_c[2]) + (pl.z - s_c[5]);
+    r = sqrtf(dx * dx + dy * dy + dz * dz);
+  }
+  const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) r = fmaxf(r, __shfl_xor(r, off));
+  if (lane == 0) s_r[wave] = r;
+  __syncthreads();
+  if (tid == 0) {
+    const float rt = fmaxf(fmaxf(s_r[0], s_r[1]), fmaxf(s_r[2], s_r[3])) * (1.0f + 0x1p-20f);
+    float4 *o = tinfo + 4 * static_cast<size_t>(blockIdx.x);
+    o[0] = make_float4(s_c[0], s_c[1], s_c[2], rt);
+    o[1] = make_float4(s_c[3], s_c[4], s_c[5], 0.0f);
+    o[2] = make_float4(fkey_value(s_box[0]), fkey_value(s_box[1]), fkey_value(s_box[2]), 0.0f);
+    o[3] = make_float4(fkey_value(s_box[3]), fkey_value(s_box[4]), fkey_value(s_box[5]), 0.0f);
+  }
+}
+
+// The wide DS kernel over sorted records (a.jpred) and sorted i-blocks:
+// workgroup b takes the i-particles iperm[512 b + tid] and
+// iperm[512 b + 256 + tid]; partials go to their own rows as in force_wide.
+template <bool NBL>
+__global__ __launch_bounds__(kWG, wide_waves<G6MI_PREC_DS>()) void force_spatial(ForceArgs a, SpatialArgs sp) {
+  constexpr int REC = rec4<G6MI_PREC_DS>();
+  constexpr int FREC = rec4<G6MI_PREC_FP32>();
+  constexpr int kLoads = kTile * REC / kWG;
+  __shared__ __attribute__((aligned(16))) float4 tile[kTile * REC];
+  __shared__ __attribute__((aligned(16))) float4 ftile[kTile * FREC];
+  __shared__ float s_ib[6];
+  const int tid = threadIdx.x;
+  const int q0 = blockIdx.x * (2 * kWG) + tid, q1 = q0 + kWG;
+  const bool v0 = q0 < a.ni, v1 = q1 < a.ni;
+  WideLanes<G6MI_PREC_DS, NBL, true> w;
+  w.init(a, v0 ? sp.iperm[q0] : 0, v1 ? sp.iperm[q1] : 0, v0, v1);
+  w.pos0 = (w.slot0 >= 0 && w.slot0 < a.nj) ? sp.inv[w.slot0] : -1;
+  w.pos1 = (w.slot1 >= 0 && w.slot1 < a.nj) ? sp.inv[w.slot1] : -1;
+  const float eps2 = static_cast<float>(a.eps2);
+
+  // box of this workgroup's i-particles (hi parts)
+  {
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (v0) {
+        lo[d] = fminf(lo[d], w.s0.xh[d]);
+        hi[d] = fmaxf(hi[d], w.s0.xh[d]);
+      }
+      if (v1) {
+        lo[d] = fminf(lo[d], w.s1.xh[d]);
+        hi[d] = fmaxf(hi[d], w.s1.xh[d]);
+      }
+    }
+    __shared__ unsigned s_ibk[6];
+    if (tid < 6) s_ibk[tid] = tid < 3 ? 0xffffffffu : 0u;
+    __syncthreads();
+    box_reduce(lo, hi, s_ibk);
+    __syncthreads();
+    if (tid < 6) s_ib[tid] = fkey_value(s_ibk[tid]);
+    __syncthreads();
+  }
+  const float ib_lo[3] = {s_ib[0], s_ib[1], s_ib[2]}, ib_hi[3] = {s_ib[3], s_ib[4], s_ib[5]};
+
+  const int ntiles = (a.nj + kTile - 1) / kTile;
+  const int per = (ntiles + gridDim.y - 1) / gridDim.y;
+  const int tb = blockIdx.y * per;
+  const int te = min(ntiles, tb + per);
+  const float4 *jp = static_cast<const float4 *>(a.jpred);
+
+  for (int tt = tb; tt < te; ++tt) {
+    const int jbase = tt * kTile;
+    const int cnt = min(kTile, a.nj - jbase);
+    __syncthreads();
+    {
+      const float4 *src = jp + static_cast<size_t>(jbase) * REC;
+      const int n4 = cnt * REC;
+#pragma unroll
+      for (int q = 0; q < kLoads; ++q) {
+        const int idx = q * kWG + tid;
+        if (idx < n4) tile[idx] = src[idx];
+      }
+    }
+    const float4 c_hi = sp.tinfo[4 * static_cast<size_t>(tt)];
+    const float4 c_lo = sp.tinfo[4 * static_cast<size_t>(tt) + 1];
+    const float4 bmin = sp.tinfo[4 * static_cast<size_t>(tt) + 2];
+    const float4 bmax = sp.tinfo[4 * static_cast<size_t>(tt) + 3];
+    const bool self_here = (w.pos0 >= jbase && w.pos0 < jbase + cnt) || (w.pos1 >= jbase && w.pos1 < jbase + cnt);
+    const int any_self = __syncthreads_or(self_here); // also the barrier after the tile load
+    float g2 = 0.0f;
+    {
+      const float tl[3] = {bmin.x, bmin.y, bmin.z}, th[3] = {bmax.x, bmax.y, bmax.z};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const float gd = fmaxf(0.0f, fmaxf(tl[d] - ib_hi[d], ib_lo[d] - th[d]));
+        g2 += gd * gd;
+      }
+    }
+    const float reach = G6MI_FAR_K * c_hi.w;
+    const bool far = cnt == kTile && !any_self && g2 >= reach * reach;
+    if (far) {
+      {
+        const float4 p = tile[tid * REC], q = tile[tid * REC + 1], v = tile[tid * REC + 2];
+        ftile[tid * FREC] = make_float4((p.x - c_hi.x) + (q.x - c_lo.x), (p.y - c_hi.y) + (q.y - c_lo.y),
+                                        (p.z - c_hi.z) + (q.z - c_lo.z), p.w);
+        ftile[tid * FREC + 1] = make_float4(v.x, v.y, v.z, q.w);
+      }
+      IState<G6MI_PREC_FP32> f0, f1;
+      const float ch[3] = {c_hi.x, c_hi.y, c_hi.z}, cl[3] = {c_lo.x, c_lo.y, c_lo.z};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        f0.x[d] = (w.s0.xh[d] - ch[d]) + (w.s0.xl[d] - cl[d]);
+        f1.x[d] = (w.s1.xh[d] - ch[d]) + (w.s1.xl[d] - cl[d]);
+        f0.v[d] = w.s0.v[d];
+        f1.v[d] = w.s1.v[d];
+      }
+      __syncthreads();
+      w.tile_far(ftile, jbase, eps2, f0, f1, a.nb_count, a.nb_slot);
+    } else {
+      w.tile(tile, jbase, cnt, eps2, a.nb_count, a.nb_slot);
+    }
+  }
+  w.resolve(jp, 0); // exact slots from the sorted records in global memory
+
+  const size_t ni = static_cast<size_t>(a.ni);
+  auto store = [&](int i, const Totals &t, float best, int bslot) {
+    double *p = a.part + static_cast<size_t>(blockIdx.y) * 7 * ni + i;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      p[d * ni] = t.acc[d];
+      p[(3 + d) * ni] = t.jrk[d];
+    }
+    p[6 * ni] = t.pot;
+    a.nn_r2[blockIdx.y * ni + i] = static_cast<double>(best);
+    a.nn_slot[blockIdx.y * ni + i] = bslot;
+  };
+  if (w.v0) store(w.row0, w.t0, w.ebest0, w.eslot0);
+  if (w.v1) store(w.row1, w.t1, w.ebest1, w.eslot1);
+}
+
+// ---------------------------------------------------------------- launchers
+
+static inline unsigned blocks256(long n) { return static_cast<unsigned>((n + 255) / 256); }
+
+hipError_t spatial_sort_bytes(int n, size_t *bytes) {
+  *bytes = 0;
+  return rocprim::radix_sort_pairs(nullptr, *bytes, static_cast<const unsigned *>(nullptr),
+                                   static_cast<unsigned *>(nullptr), static_cast<const int *>(nullptr),
+                                   static_cast<int *>(nullptr), static_cast<size_t>(n), 0, 30);
+}
+
+hipError_t launch_spatial_prep(const SpatialBufs &b, int nj, int ni, const void *jpred, const double *xi,
+                               hipStream_t s) {
+  const float4 *rec = static_cast<const float4 *>(jpred);
+  hipLaunchKernelGGL(sp_init_kernel, dim3(1), dim3(64), 0, s, b.box);
+  hipLaunchKernelGGL(sp_bbox_kernel, dim3(blocks256(nj)), dim3(256), 0, s, nj, rec, b.box);
+  hipLaunchKernelGGL(sp_jkeys_kernel, dim3(blocks256(nj)), dim3(256), 0, s, nj, rec, b.box, b.keys_in, b.vals_in);
+  size_t bytes = b.temp_bytes;
+  hipError_t e = rocprim::radix_sort_pairs(b.temp, bytes, b.keys_in, b.keys_out, b.vals_in, b.jperm,
+                                           static_cast<size_t>(nj), 0, 30, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sp_gather_kernel, dim3(blocks256(nj)), dim3(256), 0, s, nj, b.jperm, rec, b.sorted, b.inv);
+  hipLaunchKernelGGL(sp_tile_kernel, dim3(static_cast<unsigned>((nj + kTile - 1) / kTile)), dim3(256), 0, s, nj,
+                     b.sorted, b.tinfo);
+  hipLaunchKernelGGL(sp_ikeys_kernel, dim3(blocks256(ni)), dim3(256), 0, s, ni, xi, b.box, b.keys_in, b.vals_in);
+  bytes = b.temp_bytes;
+  e = rocprim::radix_sort_pairs(b.temp, bytes, b.keys_in, b.keys_out, b.vals_in, b.iperm, static_cast<size_t>(ni),
+                                0, 30, s);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_force_spatial(bool nbl, const ForceArgs &a, const SpatialBufs &b, int nsplit, hipStream_t s) {
+  if (a.ni <= 0) return hipSuccess;
+  SpatialArgs sp;
+  sp.iperm = b.iperm;
+  sp.inv = b.inv;
+  sp.tinfo = b.tinfo;
+  const dim3 grid(static_cast<unsigned>((a.ni + 2 * kWG - 1) / (2 * kWG)), static_cast<unsigned>(nsplit));
+  if (nbl)
+    hipLaunchKernelGGL(force_spatial<true>, grid, dim3(kWG), 0, s, a, sp);
+  else
+    hipLaunchKernelGGL(force_spatial<false>, grid, dim3(kWG), 0, s, a, sp);
+  return hipGetLastError();
+}
+
+} // namespace g6mi

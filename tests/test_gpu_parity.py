@@ -470,3 +470,36 @@ def test_dominant_close_companion(g6, orc, sess, prec, shape):
     rep = assert_parity(gpu, ref, jm, 1e-4, prec, f"binaries shape={shape}")
     if prec == "ds":
         assert rep["acc_max"] < 1e-6, rep
+
+
+# ------------------------------------------------- spatially ordered DS blocks
+
+SPATIAL_CASES = [(700, 1), (5000, 300), (4097, 4097), (20000, 5000), (65536, 65536)]
+
+
+@pytest.mark.parametrize("n,ni", SPATIAL_CASES)
+def test_spatial_order_parity(g6, orc, sess, n, ni):
+    """Double-single with the Morton ordering forced on (far tiles in
+    float32 relative to the tile centre): oracle parity of forces, nearest
+    neighbours and neighbour lists, including ragged tiles, own-slot tiles
+    and blocks smaller than a workgroup; and agreement with the unordered
+    kernel to the double-single error level."""
+    jm = workloads.random_cluster(n, seed=2000 + n)
+    slots = workloads.active_set(n, ni, seed=n)
+    eps2, h2 = 1e-4, 0.05
+    ref = with_xp(orc, jm, oracle_eval(orc, jm, slots, eps2, h2))
+    sess.load(jm)
+    try:
+        g6.check(sess.id, g6.g6mi_set_spatial(sess.id, 2))
+        sp = gpu_eval(sess, g6, jm, slots, ref, eps2, h2, "ds")
+        g6.check(sess.id, g6.g6mi_set_spatial(sess.id, 0))
+        plain = gpu_eval(sess, g6, jm, slots, ref, eps2, h2, "ds")
+    finally:
+        g6.g6mi_set_spatial(sess.id, 1)
+    assert_parity(sp, ref, jm, h2, "ds", f"spatial N={n} ni={ni}")
+    assert_parity(plain, ref, jm, h2, "ds", f"unordered N={n} ni={ni}")
+    # the two orders find the same neighbours (up to distance ties)
+    xp = ref["_xp"]
+    nn = parity.nn_report(sp["nn_index"], plain["nn_index"], parity.r2_to(xp, jm.index, ref["xi"], np.arange(len(slots)),
+                                                                           plain["nn_index"]), xp, jm.index, ref["xi"])
+    assert nn["ok"], nn
