@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target oracle time of the CPU baseline")
     ap.add_argument("--shape", default=None, help="i_per_group,j_splits override")
     ap.add_argument("--sweep", default=None,
-                    help="comma-separated k: also time active blocks of 2^k against all N (DS and FP64)")
+                    help="comma-separated k: also time active blocks of 2^k against all N (DS, FP32, FP64)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-cluster workload")
     ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--tune-cache", default=None, help="tuning cache file of the batched launch")
@@ -363,9 +363,9 @@ def main():
             o += [torch.empty(nk, dtype=torch.float64, device=dev), torch.empty(nk, dtype=torch.int32, device=dev),
                   torch.empty(nk, dtype=torch.float64, device=dev)]
             entry = dict(k=k, ni=nk)
-            for variant in ("ds", "fp64"):
+            for variant in ("ds", "fp32", "fp64"):
                 g6.check(hid, g6.g6mi_set_precision(hid, variant))
-                reps = max(3, min(50, int(2 ** 24 // max(1, nk))))
+                reps = max(3, min(50, int(2 ** 22 // max(1, nk))))
                 def calls(count):
                     for _ in range(count):
                         g6.check(hid, g6.g6mi_calc_device(hid, n, nk, t_islot, t_xi, t_vi, eps2, t_h2, *o,
@@ -392,7 +392,8 @@ def main():
                                       reduce_ms=round(tot["reduce_ms"] / tot["count"], 4),
                                       pairs_per_s=float(nk) * n / (ms * 1e-3),
                                       shape=g6.g6mi_get_shape(hid))
-            log(f"[bench] sweep k={k}: ds {entry['ds']['ms_per_step']} ms, fp64 {entry['fp64']['ms_per_step']} ms")
+            log(f"[bench] sweep k={k}: ds {entry['ds']['ms_per_step']} ms, fp32 {entry['fp32']['ms_per_step']} ms, "
+                f"fp64 {entry['fp64']['ms_per_step']} ms")
             sweep.append(entry)
 
     batched = None

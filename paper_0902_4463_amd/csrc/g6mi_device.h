@@ -320,8 +320,9 @@ __device__ __forceinline__ void fold(Sums<R> &ts, Totals &t) {
 
 // Per-pair path for tiles holding an own slot or the ragged end: the pair
 // terms go through group sums of kGroup pairs (float32 variants) before the
-// tile sums, as on the grouped path.
-template <int PREC, bool NBL>
+// tile sums, as on the grouped path.  FOLD: each full group goes straight
+// into the float64 totals instead (see WideLanes::tile).
+template <int PREC, bool NBL, bool FOLD = false>
 struct MaskedRun {
   using R = real_t<PREC>;
   Sums<R> g;
@@ -330,15 +331,16 @@ struct MaskedRun {
     g.zero();
     n = 0;
   }
-  __device__ __forceinline__ void step(const IState<PREC> &st, Sums<R> &ts, const float4 *rec, int jslot,
-                                       int islot, R eps2, R h2, R &best, int &bslot, int *nb_count,
+  __device__ __forceinline__ void step(const IState<PREC> &st, Sums<R> &ts, Totals &tot, const float4 *rec,
+                                       int jslot, int islot, R eps2, R h2, R &best, int &bslot, int *nb_count,
                                        int *nb_row) {
     if constexpr (PREC == G6MI_PREC_FP64) {
       pair<PREC, true, NBL>(st, ts, rec, jslot, islot, eps2, h2, best, bslot, nb_count, nb_row);
     } else {
       pair<PREC, true, NBL>(st, g, rec, jslot, islot, eps2, h2, best, bslot, nb_count, nb_row);
       if (++n == kGroup) {
-        ts.add(g);
+        if constexpr (FOLD) fold(g, tot);
+        else ts.add(g);
         start();
       }
     }
@@ -441,12 +443,17 @@ struct WideLanes {
   }
 
   // The cnt records at positions jbase .. jbase + cnt - 1 staged at tl.
+  // FOLD: the float32 group sums go straight into the float64 totals, with
+  // no float32 tile level; used where a tile gathers a particle's close
+  // neighbours (spatial order), whose large terms of both signs would
+  // otherwise cancel in one float32 tile sum.
+  template <bool FOLD = false>
   __device__ __forceinline__ void tile(const float4 *__restrict__ tl, int jbase, int cnt, R eps2,
                                        int *__restrict__ nb_count, int *__restrict__ nb_slot) {
     const bool self_here =
         (pos0 >= jbase && pos0 < jbase + cnt) || (pos1 >= jbase && pos1 < jbase + cnt);
     if (cnt < kTile || __any(self_here)) {
-      MaskedRun<PREC, NBL> r0, r1;
+      MaskedRun<PREC, NBL, FOLD> r0, r1;
       r0.start();
       r1.start();
       int *c0 = nb_count + (v0 ? row0 : 0), *c1 = nb_count + (v1 ? row1 : 0);
@@ -454,8 +461,8 @@ struct WideLanes {
       int *l1 = nb_slot + static_cast<size_t>(v1 ? row1 : 0) * kNbMax;
       for (int jj = 0; jj < cnt; ++jj) {
         const int js = jslot_at(tl, jbase, jj);
-        r0.step(s0, ts0, tl + jj * REC, js, slot0, eps2, h20, ebest0, eslot0, c0, l0);
-        r1.step(s1, ts1, tl + jj * REC, js, slot1, eps2, h21, ebest1, eslot1, c1, l1);
+        r0.step(s0, ts0, t0, tl + jj * REC, js, slot0, eps2, h20, ebest0, eslot0, c0, l0);
+        r1.step(s1, ts1, t1, tl + jj * REC, js, slot1, eps2, h21, ebest1, eslot1, c1, l1);
       }
       r0.finish(ts0);
       r1.finish(ts1);
@@ -482,8 +489,13 @@ struct WideLanes {
             m0 = fmin(m0, pair_core<PREC>(s0, g0, rec, eps2));
             m1 = fmin(m1, pair_core<PREC>(s1, g1, rec, eps2));
           }
-          ts0.add(g0);
-          ts1.add(g1);
+          if constexpr (FOLD) {
+            fold(g0, t0);
+            fold(g1, t1);
+          } else {
+            ts0.add(g0);
+            ts1.add(g1);
+          }
         }
         if (m0 < gbest0) {
           gbest0 = m0;
@@ -624,7 +636,7 @@ struct NarrowLane {
       MaskedRun<PREC, NBL> run;
       run.start();
       for (int jj = sub; jj < cnt; jj += L)
-        run.step(st, ts, tl + jj * REC, jbase + jj, slot, eps2, h2, ebest, eslot, nb_cnt, nb_row);
+        run.step(st, ts, t, tl + jj * REC, jbase + jj, slot, eps2, h2, ebest, eslot, nb_cnt, nb_row);
       run.finish(ts);
     } else {
       unsigned nbm = 0u;

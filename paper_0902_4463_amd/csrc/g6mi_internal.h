@@ -22,7 +22,7 @@ namespace g6mi {
 #define G6MI_GROUP_UNROLL 1 // groups per unrolled loop body
 #endif
 #ifndef G6MI_FAR_K
-#define G6MI_FAR_K 2.0f // far tile: gap to the i-box at least this many tile radii
+#define G6MI_FAR_K 1.0f // far tile: gap to the i-box at least this many tile radii
 #endif
 #ifndef G6MI_WIDE_WAVES
 #define G6MI_WIDE_WAVES 3 // register budget of the wide kernel: waves per SIMD (0: free)

@@ -300,7 +300,7 @@ __global__ __launch_bounds__(kWG, wide_waves<G6MI_PREC_DS>()) void force_spatial
       __syncthreads();
       w.tile_far(ftile, jbase, eps2, f0, f1, a.nb_count, a.nb_slot);
     } else {
-      w.tile(tile, jbase, cnt, eps2, a.nb_count, a.nb_slot);
+      w.template tile<true>(tile, jbase, cnt, eps2, a.nb_count, a.nb_slot);
     }
   }
   w.resolve(jp, 0); // exact slots from the sorted records in global memory
