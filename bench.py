@@ -291,7 +291,7 @@ def main():
     default_run = (args.variant == "ds" and n == 2 ** 20 and ni == n and not args.shape
                    and not args.no_neighbour_lists)
     # the library orders large double-single blocks spatially (g6mi_set_spatial)
-    spatial_run = args.variant == "ds" and ni >= 4096 and n >= 512 and not args.shape
+    spatial_run = args.variant == "ds" and ni >= 65536 and n >= 512 and not args.shape
     traffic = profiled_traffic() if default_run else None
     roofline = dict(bound="alu", achieved=round(force_tflops, 3), peak=peak, unit="TFLOP/s",
                     frac=round(force_tflops / peak, 4), traffic=traffic,

@@ -52,15 +52,24 @@ def run_one(g6, hid, jm, eta, prec, t_end, dt_max, max_steps):
         e0 = energy(jm.m, st["v"], st["pot"])
         marks, t, steps, psteps, capped = [], 0.0, 0, 0, False
         k = 1
-        while k * 0.125 <= t_end + 1e-12:
+        while k * 0.125 <= t_end + 1e-12 and not capped:
             mark = k * 0.125
-            rc, t, steps, psteps = g6.g6mi_hermite_advance(hid, mark, max(0, max_steps - steps))
-            g6.check(hid, rc)
-            if t < mark:
-                capped = True
+            # advance in eighths of the interval, reporting each one reached
+            for q in range(1, 9):
+                sub = mark - 0.125 + q * 0.125 / 8
+                rc, t, steps, psteps = g6.g6mi_hermite_advance(hid, sub, max(0, max_steps - steps))
+                g6.check(hid, rc)
+                if t < sub:
+                    capped = True
+                    break
+                print(f"[study]   N={n} eta={eta} {prec} reached t={sub:.5f} blocks={steps}", file=sys.stderr,
+                      flush=True)
+            if capped:
                 break
             st = g6.g6mi_hermite_state(hid, n)
             marks.append(dict(t=mark, dE_over_E=(energy(jm.m, st["v"], st["pot"]) - e0) / e0))
+            print(f"[study]   N={n} eta={eta} {prec} t={mark}: dE/E={marks[-1]['dE_over_E']:.3e} blocks={steps}",
+                  file=sys.stderr, flush=True)
             k += 1
         wall = time.perf_counter() - w0
         return dict(n=n, eta=eta, precision=prec, eps2=jm.meta["eps2"], t_end=t_end, t_reached=t, capped=capped,

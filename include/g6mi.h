@@ -225,7 +225,7 @@ int g6mi_get_precision(int id);
 int g6mi_set_neighbour_lists(int id, int on);
 
 /* Spatial ordering of double-single calculations: 0 off, 1 (default) for
- * blocks of at least 4096 i-particles against at least 512 j-slots, 2 for
+ * blocks of at least 65536 i-particles against at least 512 j-slots, 2 for
  * every double-single calculation.  With the ordering on, the j-records and
  * the i-block are sorted along a Morton curve of their positions, so that
  * each tile of 256 j-records and each workgroup's 512 i-particles is

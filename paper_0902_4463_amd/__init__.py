@@ -278,7 +278,7 @@ def g6mi_set_neighbour_lists(id, on) -> int:
 
 
 def g6mi_set_spatial(id, mode) -> int:
-    """0 off, 1 large double-single blocks (default), 2 every double-single calculation."""
+    """0 off, 1 double-single blocks of at least 65536 (default), 2 every double-single calculation."""
     return _L().g6mi_set_spatial(id, int(mode))
 
 

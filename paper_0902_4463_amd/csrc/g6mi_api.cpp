@@ -315,8 +315,13 @@ constexpr int kWaveTarget = G6MI_WG_PER_CU;
 constexpr int kMinTiles = 8;
 
 // Spatial ordering (g6mi_spatial.hip) for double-single blocks of at least
-// this many i-particles against at least two tiles (automatic mode).
-constexpr int kSpatialMinNi = 4096;
+// this many i-particles against at least two tiles (automatic mode).  The
+// ordering costs two sorts per call (about 0.5 ms at 2^20 j-particles) and
+// pays only when the active particles are dense enough for a workgroup's 512
+// of them to fill a compact box: measured against 2^20 Plummer j-particles,
+// random active blocks of 2^12 .. 2^14 ran slower ordered, 2^16 and up
+// faster (8% at 2^16, 17% at 2^20).
+constexpr int kSpatialMinNi = 65536;
 
 bool use_spatial(const Handle &h, int ni, int nj) {
   if (h.prec != G6MI_PREC_DS || ni <= 0 || nj <= 0) return false;
