@@ -701,6 +701,7 @@ int prepare_batch(Handle &h, int ncl, const g6mi_cluster *d_cl, int ni_total, in
   b.nj_set = nj_set;
   b.ni_total = ni_total;
   b.item_cap = static_cast<int>(item_cap);
+  b.grid = batch_grid(h, h.prec);
   b.tune = tune;
   b.jm = h.jm;
   b.fa.xi = d_xi;

@@ -28,10 +28,17 @@ namespace g6mi {
 // -------------------------------------------------------------------- plan
 
 // Work items: for cluster c with ni i-particles in nib i-blocks of ipw and
-// ntiles j-tiles in nsplit splits of `per` tiles, nib * nsplit items.  The
-// tiles per split are chosen so that every item costs about
-// item_work * 512 * kTile pair evaluations per lane group: one tile costs a
-// lane ipw pairs (narrow blocks) or 512 (wide blocks).
+// ntiles j-tiles in nsplit splits of `per` tiles, nib * nsplit items.  One
+// tile costs a lane ipw pairs (narrow blocks) or 512 (wide blocks).  Items
+// cost about the same: per = target / ipw tiles, where the target is
+// item_work * 512 lane-pairs, lowered (down to one tile) until the whole
+// batch makes at least about one item per persistent workgroup, so that a
+// batch of few or small clusters still spreads over the GPU (a single block
+// of 340 particles against 32768: 256 items instead of 16).
+//
+// Pass 1 checks the descriptors, picks the block shape of each cluster
+// (kept in its plan entry) and adds up the batch's work; pass 2 picks the
+// splits and scans items, i-blocks and partial entries.
 __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
   const int tid = threadIdx.x;
   if (blockIdx.x > 0) {
@@ -48,7 +55,7 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
     return;
   }
   __shared__ int s_items[256], s_nib[256];
-  __shared__ long long s_pent[256], s_rows[256];
+  __shared__ long long s_pent[256], s_rows[256], s_work[256];
   __shared__ int s_flags;
   if (tid == 0) s_flags = 0;
   __syncthreads();
@@ -61,8 +68,9 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
       __syncthreads();
     }
   };
-  int c_items = 0, c_nib = 0; // totals of the chunks before
-  long long c_pent = 0, c_rows = 0;
+
+  // pass 1: validity, block shape, work
+  long long c_rows = 0, work = 0;
   for (int c0 = 0; c0 < b.ncl; c0 += 256) {
     const int c = c0 + tid;
     int ni = 0, nj = 0;
@@ -98,12 +106,42 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
     }
     const int nib = ni > 0 ? (ni + ipw - 1) / ipw : 0;
     const int ntiles = (nj + kTile - 1) / kTile;
-    const int want = max(1, b.tune.item_work * (2 * kWG) / ipw);
-    int per = max(1, min(ntiles, want));
-    int nsplit = ntiles > 0 ? (ntiles + per - 1) / per : 1;
-    if (nsplit > b.tune.max_split) {
-      per = (ntiles + b.tune.max_split - 1) / b.tune.max_split;
-      nsplit = (ntiles + per - 1) / per;
+    s_work[tid] = static_cast<long long>(nib) * ntiles * ipw;
+    if (c < b.ncl) {
+      BatchPlan pl{}; // shape now, splits in pass 2
+      pl.ipw = ipw;
+      pl.log2ipw = l2;
+      pl.nib = nib;
+      pl.per = ntiles;
+      b.plan[c] = pl;
+    }
+    __syncthreads();
+    scan(s_work);
+    work += s_work[255];
+    c_rows += s_rows[255];
+    __syncthreads();
+  }
+  const long long spread = work / max(1, b.grid);
+  const long long target = max(1LL, min(static_cast<long long>(b.tune.item_work) * (2 * kWG), spread));
+
+  // pass 2: splits and the scans (each thread reads back its own pass-1 entries)
+  int c_items = 0, c_nib = 0;
+  long long c_pent = 0;
+  for (int c0 = 0; c0 < b.ncl; c0 += 256) {
+    const int c = c0 + tid;
+    int nsplit = 1, per = 1, nib = 0, ni = 0;
+    BatchPlan pl{};
+    if (c < b.ncl) {
+      pl = b.plan[c];
+      nib = pl.nib;
+      ni = nib > 0 ? b.cl[c].ni : 0;
+      const int ntiles = pl.per;
+      per = static_cast<int>(max(1LL, min(static_cast<long long>(max(ntiles, 1)), target / pl.ipw)));
+      nsplit = ntiles > 0 ? (ntiles + per - 1) / per : 1;
+      if (nsplit > b.tune.max_split) {
+        per = (ntiles + b.tune.max_split - 1) / b.tune.max_split;
+        nsplit = (ntiles + per - 1) / per;
+      }
     }
     const long long pent = static_cast<long long>(ni) * nsplit;
     s_items[tid] = nib * nsplit;
@@ -114,12 +152,8 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
     scan(s_nib);
     scan(s_pent);
     if (c < b.ncl) {
-      BatchPlan pl;
-      pl.ipw = ipw;
-      pl.log2ipw = l2;
       pl.nsplit = nsplit;
       pl.per = per;
-      pl.nib = nib;
       pl.ib0 = c_nib + s_nib[tid] - nib;
       pl.item0 = c_items + s_items[tid] - nib * nsplit;
       pl.pad = 0;
@@ -129,7 +163,6 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
     c_items += s_items[255];
     c_nib += s_nib[255];
     c_pent += s_pent[255];
-    c_rows += s_rows[255];
     __syncthreads();
   }
   // item -> cluster table; each thread fills the items of its own clusters

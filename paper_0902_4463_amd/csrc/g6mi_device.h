@@ -678,15 +678,17 @@ struct NarrowLane {
     resolve_group<PREC>(st, grp, L, src, base, ebest, eslot);
   }
 
-  // Add the L lane totals of each i-particle in lane order through `red`
-  // (LDS, [9][kWG] doubles; the caller synchronises before reusing it).
-  // Afterwards the lanes with sub == 0 hold the i-particle's totals in t
-  // and its nearest-neighbour candidate in (bestd, bslot).
+  // Add the L lane totals of each i-particle through `red` (LDS, [9][kWG]
+  // doubles; the caller synchronises before reusing it) in a fixed binary
+  // tree: at each level lane `sub` < half adds lane sub + half.  Afterwards
+  // the lanes with sub == 0 hold the i-particle's totals in t and its
+  // nearest-neighbour candidate in (bestd, bslot).
   __device__ __forceinline__ void lane_sum(double *red, int tid, int il, int ipw, double &bestd,
                                            int &bslot) {
     bestd = static_cast<double>(ebest);
     bslot = eslot;
     if (L == 1) return;
+    int *rslot = reinterpret_cast<int *>(red + 8 * kWG);
     __syncthreads();
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -695,11 +697,11 @@ struct NarrowLane {
     }
     red[6 * kWG + tid] = t.pot;
     red[7 * kWG + tid] = bestd;
-    reinterpret_cast<int *>(red + 8 * kWG)[tid] = bslot;
-    __syncthreads();
-    if (sub == 0) {
-      for (int q = 1; q < L; ++q) {
-        const int o = q * ipw + il;
+    rslot[tid] = bslot;
+    for (int half = L >> 1; half > 0; half >>= 1) {
+      __syncthreads();
+      if (sub < half) {
+        const int o = (sub + half) * ipw + il;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
           t.acc[d] += red[d * kWG + o];
@@ -707,11 +709,22 @@ struct NarrowLane {
         }
         t.pot += red[6 * kWG + o];
         const double r2o = red[7 * kWG + o];
-        const int so = reinterpret_cast<const int *>(red + 8 * kWG)[o];
+        const int so = rslot[o];
         if (so >= 0 && (r2o < bestd || (r2o == bestd && (bslot < 0 || so < bslot)))) {
           bestd = r2o;
           bslot = so;
         }
+      }
+      __syncthreads();
+      if (sub < half) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          red[d * kWG + tid] = t.acc[d];
+          red[(3 + d) * kWG + tid] = t.jrk[d];
+        }
+        red[6 * kWG + tid] = t.pot;
+        red[7 * kWG + tid] = bestd;
+        rslot[tid] = bslot;
       }
     }
   }

@@ -169,6 +169,7 @@ struct BatchArgs {
   int *item_cl = nullptr;           // [item_cap] cluster of each work item
   BatchWork *work = nullptr;
   int ncl = 0, nj_set = 0, ni_total = 0, item_cap = 0;
+  int grid = 1;            // persistent workgroups of batch_kernel
   BatchTune tune;
   JMem jm;
   ForceArgs fa;            // i-arrays over rows 0..ni_total-1; nb_count, nb_slot
