@@ -314,15 +314,17 @@ int g6mi_last_status(int id, int *flags);
  * j-slot holding row r's own particle, or -1; d_xi, d_vi [ni_total][3];
  * d_h2 [ni_total]), and so are the outputs (d_acc, d_jerk [ni_total][3],
  * d_pot, d_nnb, d_r2nn [ni_total]; d_nnb and d_r2nn may be NULL).  Row r of
- * cluster c gets, exactly as a separate g6mi_calc_device on that cluster
- * alone would give (up to the order of float64 additions), the forces of
+ * cluster c gets, as a separate g6mi_calc_device on that cluster alone
+ * would give (up to the order of the force sums: the batch may cut a block
+ * into other i-blocks and j-splits), the forces of
  * c's j-slots predicted to c's ti and softened by c's eps2 (Sec. 2.2-2.3),
  * its nearest neighbour among them, and its neighbour list (read afterwards
  * with g6_read_neighbour_list / g6_get_neighbour_list, ipipe = r).
  *
- * One plan kernel and one persistent kernel: work items (cluster, i-block,
- * j-split) are taken from a queue, each predicts its j-tiles in on-chip
- * memory and the last split of each i-block writes the results.  All work
+ * A plan kernel, a persistent kernel and a reduction kernel: work items
+ * (cluster, i-block, j-split) are taken from a queue, each predicting its
+ * j-tiles in on-chip memory; then each i-block's split partials are added
+ * and its rows written.  All work
  * is enqueued on `stream` (NULL: the handle's stream) without host
  * synchronisation.  The caller keeps every device buffer valid until the
  * work has completed (and the i-arrays until g6_read_neighbour_list).

@@ -143,7 +143,7 @@ struct Handle {
   // batched calculations
   BatchTune btune;
   int b_wg_per_cu = 0; // 0: as many as the kernel's occupancy allows
-  DevBuf d_cl, d_plan, d_items, d_bwork, d_ibcnt;
+  DevBuf d_cl, d_plan, d_items, d_bwork, d_ibcl;
   PinBuf h_cl;
   hipEvent_t cl_ev = nullptr;
   bool cl_busy = false;
@@ -359,13 +359,15 @@ int ensure_spatial(Handle &h, int nj, int ni) {
   HIPCHK(&h, spatial_sort_bytes(static_cast<int>(n), &temp));
   auto al = [](size_t b) { return round_up(std::max<size_t>(b, 1), 256); };
   const size_t sizes[] = {al(6 * sizeof(unsigned)), al(n * 4), al(n * 4), al(n * 4), al(j * 4), al(i * 4),
-                          al(j * 4), al(j * 48), al(ntiles * 64), al(temp)};
+                          al(j * 4), al(j * 48), al(ntiles * 64), al(i * 24), al(i * 24), al(i * 8), al(i * 4),
+                          al(i * 4), al(temp)};
+  constexpr int kParts = sizeof(sizes) / sizeof(sizes[0]);
   size_t total = 0;
   for (size_t b : sizes) total += b;
   HIPCHK(&h, ensure(h.d_sp, total));
   char *p = static_cast<char *>(h.d_sp.p);
-  void *parts[10];
-  for (int k = 0; k < 10; ++k) {
+  void *parts[kParts];
+  for (int k = 0; k < kParts; ++k) {
     parts[k] = p;
     p += sizes[k];
   }
@@ -379,8 +381,13 @@ int ensure_spatial(Handle &h, int nj, int ni) {
   b.inv = static_cast<int *>(parts[6]);
   b.sorted = static_cast<float4 *>(parts[7]);
   b.tinfo = static_cast<float4 *>(parts[8]);
-  b.temp = parts[9];
-  b.temp_bytes = sizes[9];
+  b.sxi = static_cast<double *>(parts[9]);
+  b.svi = static_cast<double *>(parts[10]);
+  b.sh2 = static_cast<double *>(parts[11]);
+  b.sislot = static_cast<int *>(parts[12]);
+  b.spos = static_cast<int *>(parts[13]);
+  b.temp = parts[14];
+  b.temp_bytes = sizes[14];
   return 0;
 }
 
@@ -423,7 +430,7 @@ int enqueue_calc(Handle &h, int nj, int ni, const int *d_islot, const double *d_
   if (ev) HIPCHK(&h, hipEventRecord(ev[0], s));
   HIPCHK(&h, launch_predict(h.prec, nj, h.ti, h.jm, h.d_pred.p,
                             static_cast<int *>(h.d_nbcount.p), ni, status, s));
-  if (spatial) HIPCHK(&h, launch_spatial_prep(h.sp, nj, ni, h.d_pred.p, d_xi, s));
+  if (spatial) HIPCHK(&h, launch_spatial_prep(h.sp, nj, ni, h.d_pred.p, d_xi, d_vi, d_h2, d_islot, s));
   if (ev) HIPCHK(&h, hipEventRecord(ev[1], s));
   ForceArgs a;
   a.jpred = h.d_pred.p;
@@ -442,15 +449,13 @@ int enqueue_calc(Handle &h, int nj, int ni, const int *d_islot, const double *d_
   a.nb_count = static_cast<int *>(h.d_nbcount.p);
   a.nb_slot = static_cast<int *>(h.d_nblist.p);
   if (spatial) {
-    ForceArgs as = a;
-    as.jpred = h.sp.sorted;
-    HIPCHK(&h, launch_force_spatial(h.nbl, as, h.sp, nsplit, s));
+    HIPCHK(&h, launch_force_spatial(h.nbl, a, h.sp, nsplit, s));
   } else {
     HIPCHK(&h, launch_force(h.prec, h.nbl, a, nsplit, s));
   }
   if (ev) HIPCHK(&h, hipEventRecord(ev[2], s));
-  HIPCHK(&h, launch_reduce(nsplit, ni, a.part, a.nn_r2, a.nn_slot, h.jm.index, a.nb_count,
-                           a.nb_slot, h.nbl, d_acc, d_jerk, d_pot, d_nnb, d_r2nn, status,
+  HIPCHK(&h, launch_reduce(nsplit, ni, spatial ? h.sp.iperm : nullptr, a.part, a.nn_r2, a.nn_slot, h.jm.index,
+                           a.nb_count, a.nb_slot, h.nbl, d_acc, d_jerk, d_pot, d_nnb, d_r2nn, status,
                            static_cast<int *>(h.d_ovf.p), s));
   if (ev) {
     HIPCHK(&h, hipEventRecord(ev[3], s));
@@ -623,7 +628,7 @@ std::vector<uint64_t> graph_key(const Handle &h, const BatchArgs &b, int grid, h
           static_cast<uint64_t>(b.tune.wide_min), static_cast<uint64_t>(b.tune.max_split),
           u(b.jm.t), static_cast<uint64_t>(b.jm.cap), u(b.fa.xi), u(b.fa.vi), u(b.fa.h2),
           u(b.fa.islot), u(b.fa.nb_count), u(b.fa.nb_slot), u(b.part), u(b.nn_r2), u(b.nn_slot),
-          static_cast<uint64_t>(b.pcap), u(b.ibcnt), static_cast<uint64_t>(b.nbl), u(b.acc),
+          static_cast<uint64_t>(b.pcap), u(b.ib_cl), static_cast<uint64_t>(b.nbl), u(b.acc),
           u(b.jerk), u(b.pot), u(b.r2nn), u(b.nnb), u(b.status), u(b.ovf_list), u(b.ovf_tag),
           static_cast<uint64_t>(h.prec), static_cast<uint64_t>(grid), u(s)};
 }
@@ -677,13 +682,14 @@ int prepare_batch(Handle &h, int ncl, const g6mi_cluster *d_cl, int ni_total, in
   BatchTune tune = h.btune;
   const size_t fit = kBatchPartialBudget / (n * kPartialEntryBytes);
   tune.max_split = static_cast<int>(std::max<size_t>(1, std::min<size_t>(tune.max_split, fit)));
-  const size_t item_cap = (n / 256 + static_cast<size_t>(ncl) + 1) * static_cast<size_t>(tune.max_split);
+  const size_t item_cap =
+      (n / kBatchMinIpw + static_cast<size_t>(ncl) + 1) * static_cast<size_t>(tune.max_split);
   if (item_cap > static_cast<size_t>(INT_MAX)) return fail(&h, G6MI_EINVAL, "batch too large");
   const size_t pcap = n * static_cast<size_t>(tune.max_split);
   HIPCHK(&h, ensure(h.d_plan, std::max(ncl, 1) * sizeof(BatchPlan)));
   HIPCHK(&h, ensure(h.d_items, item_cap * sizeof(int)));
   HIPCHK(&h, ensure(h.d_bwork, sizeof(BatchWork)));
-  HIPCHK(&h, ensure(h.d_ibcnt, n * sizeof(int)));
+  HIPCHK(&h, ensure(h.d_ibcl, n * sizeof(int)));
   HIPCHK(&h, ensure(h.d_part, 7 * pcap * sizeof(double)));
   HIPCHK(&h, ensure(h.d_nnr2, pcap * sizeof(double)));
   HIPCHK(&h, ensure(h.d_nnslot, pcap * sizeof(int)));
@@ -715,7 +721,7 @@ int prepare_batch(Handle &h, int ncl, const g6mi_cluster *d_cl, int ni_total, in
   b.nn_r2 = static_cast<double *>(h.d_nnr2.p);
   b.nn_slot = static_cast<int *>(h.d_nnslot.p);
   b.pcap = pcap;
-  b.ibcnt = static_cast<int *>(h.d_ibcnt.p);
+  b.ib_cl = static_cast<int *>(h.d_ibcl.p);
   b.nbl = h.nbl ? 1 : 0;
   b.acc = d_acc;
   b.jerk = d_jerk;
@@ -878,7 +884,7 @@ G6MI_API int g6_close(int id) {
   h->hs.h_ctl.release();
   for (DevBuf *b : {&h->d_jm, &h->d_pred, &h->d_stage, &h->d_i, &h->d_out, &h->d_part,
                     &h->d_nnr2, &h->d_nnslot, &h->d_nbcount, &h->d_nblist, &h->d_flags,
-                    &h->d_ovf, &h->d_cl, &h->d_plan, &h->d_items, &h->d_bwork, &h->d_ibcnt, &h->d_sp})
+                    &h->d_ovf, &h->d_cl, &h->d_plan, &h->d_items, &h->d_bwork, &h->d_ibcl, &h->d_sp})
     b->release();
   for (PinBuf *b : {&h->h_stage, &h->h_i, &h->h_out, &h->h_cl}) b->release();
   if (h->cl_ev) (void)hipEventDestroy(h->cl_ev);
@@ -1537,6 +1543,14 @@ int hs_read_ctl(Handle &h, hipStream_t s, HermiteCtl &c) {
 }
 } // namespace
 
+// Order key of a double, as the device kernels map block times onto
+// unsigned 64-bit keys (a larger double gives a larger key).
+uint64_t order_key_host(double x) {
+  uint64_t b;
+  std::memcpy(&b, &x, sizeof(b));
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
 G6MI_API int g6mi_hermite_init(int id, int n, double eps2, double h2, double eta, double eta_s, double dt_max,
                                double dt_min) {
   Handle *h = get_open(id);
@@ -1593,7 +1607,11 @@ G6MI_API int g6mi_hermite_init(int id, int n, double eps2, double h2, double eta
   hs.cap = cap;
   hs.jm_t = h->jm.t;
   HermiteCtl c{};
-  c.tnext_key = 0xfff0000000000000ull;
+  // the first block: every particle, due at t0 (steps are zero until the
+  // first force evaluation)
+  c.key[0] = order_key_host(t0);
+  c.key[1] = 0xfff0000000000000ull; // +inf
+  c.phase = 0;
   c.t_end = INFINITY;
   c.time = t0;
   c.desc = g6mi_cluster{0, n, 0, 0, t0, eps2};

@@ -11,10 +11,10 @@
 //                         straight into LDS from the float64 j-memory (the
 //                         predictor of Sec. 2.2 fused into the tile load),
 //                         runs the interaction of Sec. 2.3 on them and stores
-//                         its split partials; the last split of an i-block to
-//                         finish adds the partials of all splits in split
-//                         order and writes the results (the reduction of
-//                         Sec. 2.3 fused into the same launch).
+//                         its split partials.
+//   batch_reduce       -- one workgroup per i-block adds the partials of all
+//                         its splits in a fixed order and writes the results
+//                         (the reduction of Sec. 2.3).
 //   batch_nb_exact     -- exact neighbour lists for overflowed i-particles.
 //
 // Each cluster is what the paper's library evaluates per call; batching them
@@ -27,14 +27,48 @@ namespace g6mi {
 
 // -------------------------------------------------------------------- plan
 
+// Inclusive sum of x over the 256 threads of a workgroup (wave shuffles, then
+// the four wave totals through LDS); all = the workgroup total.  Every
+// thread must call it; it ends with a barrier, so s_part can be reused.
+template <class T> __device__ __forceinline__ T wg_scan(T x, T *s_part, T &all) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) s_part[wave] = x;
+  __syncthreads();
+  T base = 0, sum = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const T p = s_part[w];
+    if (w < wave) base += p;
+    sum += p;
+  }
+  __syncthreads();
+  all = sum;
+  return x + base;
+}
+
+// Index of the first of 256 non-decreasing counts above q (one exists).
+__device__ __forceinline__ int first_above(const int *inc, int q) {
+  int lo = 0, hi = 255;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (inc[mid] > q) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
 // Work items: for cluster c with ni i-particles in nib i-blocks of ipw and
 // ntiles j-tiles in nsplit splits of `per` tiles, nib * nsplit items.  One
 // tile costs a lane ipw pairs (narrow blocks) or 512 (wide blocks).  Items
 // cost about the same: per = target / ipw tiles, where the target is
 // item_work * 512 lane-pairs, lowered (down to one tile) until the whole
 // batch makes at least about one item per persistent workgroup, so that a
-// batch of few or small clusters still spreads over the GPU (a single block
-// of 340 particles against 32768: 256 items instead of 16).
+// batch of few or small clusters still spreads over the GPU.
 //
 // Pass 1 checks the descriptors, picks the block shape of each cluster
 // (kept in its plan entry) and adds up the batch's work; pass 2 picks the
@@ -42,32 +76,20 @@ namespace g6mi {
 __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
   const int tid = threadIdx.x;
   if (blockIdx.x > 0) {
-    // rows (blockIdx.x - 1) * chunk ...: i-block arrival counters (at most
-    // one i-block per row) and neighbour counts
+    // rows (blockIdx.x - 1) * chunk ...: neighbour counts
     const int base = (blockIdx.x - 1) * kPlanZeroChunk;
-    for (int k = tid; k < kPlanZeroChunk; k += 256) {
-      const int r = base + k;
-      if (r < b.ni_total) {
-        b.ibcnt[r] = 0;
-        if (b.nbl) b.fa.nb_count[r] = 0;
+    if (b.nbl)
+      for (int k = tid; k < kPlanZeroChunk; k += 256) {
+        const int r = base + k;
+        if (r < b.ni_total) b.fa.nb_count[r] = 0;
       }
-    }
     return;
   }
-  __shared__ int s_items[256], s_nib[256];
-  __shared__ long long s_pent[256], s_rows[256], s_work[256];
+  __shared__ long long s_part[4];
+  __shared__ int s_inc[256], s_inc_ib[256];
   __shared__ int s_flags;
   if (tid == 0) s_flags = 0;
   __syncthreads();
-  // inclusive scans over one chunk of 256 clusters
-  auto scan = [&](auto *a) {
-    for (int off = 1; off < 256; off <<= 1) {
-      const auto x = tid >= off ? a[tid - off] : 0;
-      __syncthreads();
-      a[tid] += x;
-      __syncthreads();
-    }
-  };
 
   // pass 1: validity, block shape, work
   long long c_rows = 0, work = 0;
@@ -86,10 +108,9 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
     // Clusters sharing i-rows could add up to more rows than ni_total, and
     // the i-block counters and partial sums are sized by ni_total: every
     // cluster past that many rows in total is skipped.
-    s_rows[tid] = ni;
-    __syncthreads();
-    scan(s_rows);
-    if (ok && c_rows + s_rows[tid] > b.ni_total) {
+    long long rows_all;
+    const long long rows = wg_scan<long long>(ni, s_part, rows_all);
+    if (ok && c_rows + rows > b.ni_total) {
       ok = false;
       ni = nj = 0;
     }
@@ -106,25 +127,59 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
     }
     const int nib = ni > 0 ? (ni + ipw - 1) / ipw : 0;
     const int ntiles = (nj + kTile - 1) / kTile;
-    s_work[tid] = static_cast<long long>(nib) * ntiles * ipw;
     if (c < b.ncl) {
       BatchPlan pl{}; // shape now, splits in pass 2
       pl.ipw = ipw;
       pl.log2ipw = l2;
       pl.nib = nib;
       pl.per = ntiles;
+      pl.ni = ni;
       b.plan[c] = pl;
     }
-    __syncthreads();
-    scan(s_work);
-    work += s_work[255];
-    c_rows += s_rows[255];
-    __syncthreads();
+    long long work_all;
+    wg_scan<long long>(static_cast<long long>(nib) * ntiles * ipw, s_part, work_all);
+    work += work_all;
+    c_rows += rows_all;
+  }
+  // pass 1b: a cluster whose i-blocks cannot make its share of the
+  // persistent workgroups even with the most splits (one tile each, at most
+  // max_split) takes smaller i-blocks, down to kBatchMinIpw, with more lanes
+  // per i-particle: a lone block of 340 against 32768 particles then runs as
+  // 11 blocks of 32 in 704 items instead of 2 blocks of 256 in 128 items
+  const long long work0 = max(1LL, work);
+  work = 0;
+  for (int c0 = 0; c0 < b.ncl; c0 += 256) {
+    const int c = c0 + tid;
+    long long w = 0;
+    if (c < b.ncl) {
+      BatchPlan pl = b.plan[c];
+      if (pl.nib > 0) {
+        const int ni = pl.ni;
+        const int ntiles = pl.per;
+        const long long share = (static_cast<long long>(b.grid) * pl.nib * ntiles * pl.ipw + work0 - 1) / work0;
+        const int most = min(max(ntiles, 1), b.tune.max_split);
+        if (static_cast<long long>(pl.nib) * most < share) {
+          while (pl.ipw > kBatchMinIpw && static_cast<long long>(pl.nib) * most < share) {
+            pl.ipw = min(pl.ipw >> 1, kWG);
+            pl.log2ipw = __builtin_ctz(pl.ipw);
+            pl.nib = (ni + pl.ipw - 1) / pl.ipw;
+          }
+          b.plan[c] = pl;
+        }
+        w = static_cast<long long>(pl.nib) * ntiles * pl.ipw;
+      }
+    }
+    long long work_all;
+    wg_scan<long long>(w, s_part, work_all);
+    work += work_all;
   }
   const long long spread = work / max(1, b.grid);
   const long long target = max(1LL, min(static_cast<long long>(b.tune.item_work) * (2 * kWG), spread));
 
-  // pass 2: splits and the scans (each thread reads back its own pass-1 entries)
+  // pass 2: splits, the scans (each thread reads back its own pass-1 entries)
+  // and the item -> cluster and i-block -> cluster tables, filled by all
+  // threads: item (i-block) q of the chunk belongs to the first cluster whose
+  // inclusive item (i-block) count exceeds q
   int c_items = 0, c_nib = 0;
   long long c_pent = 0;
   for (int c0 = 0; c0 < b.ncl; c0 += 256) {
@@ -134,7 +189,7 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
     if (c < b.ncl) {
       pl = b.plan[c];
       nib = pl.nib;
-      ni = nib > 0 ? b.cl[c].ni : 0;
+      ni = pl.ni;
       const int ntiles = pl.per;
       per = static_cast<int>(max(1LL, min(static_cast<long long>(max(ntiles, 1)), target / pl.ipw)));
       nsplit = ntiles > 0 ? (ntiles + per - 1) / per : 1;
@@ -144,35 +199,29 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
       }
     }
     const long long pent = static_cast<long long>(ni) * nsplit;
-    s_items[tid] = nib * nsplit;
-    s_nib[tid] = nib;
-    s_pent[tid] = pent;
-    __syncthreads();
-    scan(s_items);
-    scan(s_nib);
-    scan(s_pent);
+    long long items_all, nib_all, pent_all;
+    const int items = static_cast<int>(wg_scan<long long>(static_cast<long long>(nib) * nsplit, s_part, items_all));
+    const int nibs = static_cast<int>(wg_scan<long long>(nib, s_part, nib_all));
+    const long long pents = wg_scan<long long>(pent, s_part, pent_all);
     if (c < b.ncl) {
       pl.nsplit = nsplit;
       pl.per = per;
-      pl.ib0 = c_nib + s_nib[tid] - nib;
-      pl.item0 = c_items + s_items[tid] - nib * nsplit;
-      pl.pad = 0;
-      pl.pbase = c_pent + s_pent[tid] - pent;
+      pl.ib0 = c_nib + nibs - nib;
+      pl.item0 = c_items + items - nib * nsplit;
+      pl.pbase = c_pent + pents - pent;
       b.plan[c] = pl;
     }
-    c_items += s_items[255];
-    c_nib += s_nib[255];
-    c_pent += s_pent[255];
+    s_inc[tid] = items;
+    s_inc_ib[tid] = nibs;
     __syncthreads();
+    for (int q = tid; q < items_all; q += 256)
+      if (c_items + q < b.item_cap) b.item_cl[c_items + q] = c0 + first_above(s_inc, q);
+    for (int q = tid; q < nib_all; q += 256) b.ib_cl[c_nib + q] = c0 + first_above(s_inc_ib, q);
+    __syncthreads(); // s_inc, s_inc_ib are rewritten by the next chunk
+    c_items += static_cast<int>(items_all);
+    c_nib += static_cast<int>(nib_all);
+    c_pent += pent_all;
   }
-  // item -> cluster table; each thread fills the items of its own clusters
-  // (a thread reads back only the plan entries it wrote itself)
-  for (int c = tid; c < b.ncl; c += 256) {
-    const BatchPlan pl = b.plan[c];
-    const int end = min(pl.item0 + pl.nib * pl.nsplit, b.item_cap);
-    for (int q = pl.item0; q < end; ++q) b.item_cl[q] = c;
-  }
-  __syncthreads();
   if (tid == 0) {
     b.work->head = 0;
     b.work->nitems = min(c_items, b.item_cap);
@@ -207,7 +256,7 @@ __global__ __launch_bounds__(kWG, wide_waves<PREC>()) void batch_kernel(BatchArg
   using R = real_t<PREC>;
   constexpr int REC = rec4<PREC>();
   __shared__ __attribute__((aligned(16))) unsigned char lds[narrow_lds_bytes<PREC>()];
-  __shared__ int s_item, s_last;
+  __shared__ int s_item;
   float4 *tile = reinterpret_cast<float4 *>(lds);
   const int tid = threadIdx.x;
   const int nitems = b.work->nitems;
@@ -269,28 +318,44 @@ __global__ __launch_bounds__(kWG, wide_waves<PREC>()) void batch_kernel(BatchArg
       if (n.sub == 0 && n.valid) store_partial(b, e0 + il, n.t, bestd, bslot);
     }
 
-    // The last split of the i-block to arrive finishes its i-particles.
-    // Release: every lane's partial and neighbour stores are made visible
-    // device-wide before the arrival is counted; acquire on the other side.
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) s_last = atomicAdd(b.ibcnt + p.ib0 + ib, 1) == p.nsplit - 1;
-    __syncthreads();
-    if (__builtin_amdgcn_readfirstlane(s_last)) {
-      __threadfence();
-      const int ipw = p.ipw;
-      int fl = 0;
-      for (int k = tid; k < ipw; k += kWG) {
-        const int il = ib * ipw + k;
-        if (il < d.ni) {
-          const size_t e = static_cast<size_t>(p.pbase) + il;
-          fl |= finish_row(p.nsplit, b.part + e, static_cast<size_t>(d.ni), b.pcap, b.nn_r2 + e, b.nn_slot + e,
-                           static_cast<size_t>(d.ni), d.ioff + il, b.jm.index, b.fa.nb_count, b.fa.nb_slot, NBL,
+  }
+}
+
+// One workgroup per i-block (grid-strided over the work->nib i-blocks of the
+// batch, ib_cl giving each one's cluster): the float64 sum of the i-block's
+// split partials (split_sum, G lanes per i-particle as the splits and the
+// workgroup allow) and the rows' results (finish_out).  A launch of its own:
+// the kernel boundary makes every item's partials visible, where a release
+// fence per item would write back the XCD's whole L2 (buffer_wbl2) and an
+// acquire invalidate it, once per item.
+__global__ __launch_bounds__(kWG) void batch_reduce_kernel(BatchArgs b) {
+  const int tid = threadIdx.x;
+  const int nib_total = b.work->nib;
+  for (int ibg = blockIdx.x; ibg < nib_total; ibg += gridDim.x) {
+    const int c = __builtin_amdgcn_readfirstlane(b.ib_cl[ibg]);
+    const g6mi_cluster d = b.cl[c];
+    const BatchPlan p = b.plan[c];
+    const int ib = ibg - p.ib0;
+    const int ipw = p.ipw;
+    const int G = min(split_lanes(p.nsplit, 1), max(1, kWG / ipw));
+    int ioff, g, xs;
+    split_lane_map(tid & 63, G, ioff, g, xs);
+    int fl = 0;
+    for (int k0 = 0; k0 < ipw; k0 += kWG / G) {
+      const int k = k0 + (tid >> 6) * xs + ioff;
+      const int il = ib * ipw + k;
+      if (k < ipw && il < d.ni) {
+        const size_t e = static_cast<size_t>(p.pbase) + il;
+        double sum[7], best;
+        int bslot;
+        split_sum(p.nsplit, G, g, xs, b.part + e, static_cast<size_t>(d.ni), b.pcap, b.nn_r2 + e, b.nn_slot + e,
+                  static_cast<size_t>(d.ni), sum, best, bslot);
+        if (g == 0)
+          fl |= finish_out(sum, best, bslot, d.ioff + il, b.jm.index, b.fa.nb_count, b.fa.nb_slot, b.nbl != 0,
                            b.acc, b.jerk, b.pot, b.nnb, b.r2nn, b.status, b.ovf_list, b.ovf_tag, c);
-        }
       }
-      if (fl) atomicOr(b.status + kStatusFlags, fl);
     }
+    if (fl) atomicOr(b.status + kStatusFlags, fl);
   }
 }
 
@@ -344,6 +409,7 @@ hipError_t launch_batch_force(int prec, const BatchArgs &b, int grid, hipStream_
   case G6MI_PREC_DS: launch_batch_prec<G6MI_PREC_DS>(b, grid, s); break;
   default: launch_batch_prec<G6MI_PREC_FP64>(b, grid, s);
   }
+  hipLaunchKernelGGL(batch_reduce_kernel, dim3(grid), dim3(kWG), 0, s, b);
   return hipGetLastError();
 }
 

@@ -745,39 +745,86 @@ template <int PREC> constexpr int wide_waves() {
 
 // ------------------------------------------------------------ finalisation
 
-// Final result of one i-particle from its nsplit j-split partials: the
-// float64 sum in split order, the lexicographic (r^2, slot) minimum of the
-// nearest-neighbour candidates, and the neighbour list turned from slots
-// into particle indices sorted ascending.  Component c of split s is at
-// part[s * sstride + c * cstride]; the candidates at nn_r2[s * nstride],
-// nn_slot[s * nstride] (pointers already at the i-particle).  Outputs go to
-// row `row`.  An overflowed list is queued in ovf_list (and its tag in
+// Nearest-neighbour candidate (r2, sl) merged into (best, bslot): the
+// lexicographic (r^2, slot) minimum over valid slots, so the merge order
+// does not matter.
+__device__ __forceinline__ void nn_merge(double r2, int sl, double &best, int &bslot) {
+  if (sl >= 0 && (r2 < best || (r2 == best && (bslot < 0 || sl < bslot)))) {
+    best = r2;
+    bslot = sl;
+  }
+}
+
+// The nsplit j-split partials of one i-particle added by a group of G lanes
+// (G a power of two up to 64) of one wave, every lane of the group active:
+// lane g of the group sits xs lanes after lane g - 1 (split_lane_map puts
+// the G lanes of an i-particle xs = 64 / G apart, so that the lanes with the
+// same g read consecutive i-particles).  Component c of split q is at
+// part[q * sstride + c * cstride]; the candidates at nn_r2[q * nstride],
+// nn_slot[q * nstride].  Lane g adds splits g, g + G, g + 2G, ... in that
+// order in float64, its loads issued kAhead splits ahead of the additions
+// (latency, not bandwidth, bounds a long sum); the G lane sums then meet in
+// a butterfly of xor exchanges.  Each exchange adds two equal pairs of
+// operands in either order, so all lanes of the group end with the same
+// bits, and the order of additions is fixed by nsplit and G alone.  G = 1
+// is the plain sum in split order.
+__device__ __forceinline__ void split_sum(int nsplit, int G, int g, int xs, const double *__restrict__ part,
+                                          size_t sstride, size_t cstride, const double *__restrict__ nn_r2,
+                                          const int *__restrict__ nn_slot, size_t nstride, double s[7],
+                                          double &best, int &bslot) {
+  constexpr int kAhead = 4;
+#pragma unroll
+  for (int c = 0; c < 7; ++c) s[c] = 0.0;
+  best = INFINITY;
+  bslot = -1;
+  int q = g;
+  for (; q + (kAhead - 1) * G < nsplit; q += kAhead * G) {
+    double v[kAhead][7], r2[kAhead];
+    int sl[kAhead];
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u) {
+      const size_t k = static_cast<size_t>(q + u * G);
+#pragma unroll
+      for (int c = 0; c < 7; ++c) v[u][c] = part[k * sstride + c * cstride];
+      r2[u] = nn_r2[k * nstride];
+      sl[u] = nn_slot[k * nstride];
+    }
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u) {
+#pragma unroll
+      for (int c = 0; c < 7; ++c) s[c] += v[u][c];
+      nn_merge(r2[u], sl[u], best, bslot);
+    }
+  }
+  for (; q < nsplit; q += G) {
+    const size_t k = static_cast<size_t>(q);
+#pragma unroll
+    for (int c = 0; c < 7; ++c) s[c] += part[k * sstride + c * cstride];
+    nn_merge(nn_r2[k * nstride], nn_slot[k * nstride], best, bslot);
+  }
+  for (int m = 1; m < G; m <<= 1) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) s[c] += __shfl_xor(s[c], m * xs);
+    const double ob = __shfl_xor(best, m * xs);
+    const int os = __shfl_xor(bslot, m * xs);
+    nn_merge(ob, os, best, bslot);
+  }
+}
+
+// Final result of one i-particle from its summed partials s (acc xyz, jerk
+// xyz, sum m/r) and nearest-neighbour candidate: outputs go to row `row`,
+// and its neighbour list is turned from slots into particle indices sorted
+// ascending.  An overflowed list is queued in ovf_list (and its tag in
 // ovf_tag when given) for the exact pass, counted in
 // status[kStatusOverflowCount].  Returns the status flags of the row
 // (bit 0 non-finite output, bit 1 neighbour overflow).
-__device__ __forceinline__ int finish_row(int nsplit, const double *__restrict__ part, size_t sstride,
-                                          size_t cstride, const double *__restrict__ nn_r2,
-                                          const int *__restrict__ nn_slot, size_t nstride, int row,
+__device__ __forceinline__ int finish_out(const double s[7], double best, int bslot, int row,
                                           const int *__restrict__ jindex,
                                           const int *__restrict__ nb_count, int *__restrict__ nb_slot,
                                           bool nbl, double *__restrict__ acc, double *__restrict__ jerk,
                                           double *__restrict__ pot, int *__restrict__ nnb,
                                           double *__restrict__ r2nn, int *__restrict__ status,
                                           int *__restrict__ ovf_list, int *__restrict__ ovf_tag, int tag) {
-  double s[7] = {0, 0, 0, 0, 0, 0, 0};
-  double best = INFINITY;
-  int bslot = -1;
-  for (int q = 0; q < nsplit; ++q) {
-    const double *p = part + static_cast<size_t>(q) * sstride;
-#pragma unroll
-    for (int c = 0; c < 7; ++c) s[c] += p[c * cstride];
-    const double r2 = nn_r2[q * nstride];
-    const int sl = nn_slot[q * nstride];
-    if (sl >= 0 && (r2 < best || (r2 == best && (bslot < 0 || sl < bslot)))) {
-      best = r2;
-      bslot = sl;
-    }
-  }
   const size_t i = static_cast<size_t>(row);
   bool finite = true;
 #pragma unroll
@@ -813,6 +860,26 @@ __device__ __forceinline__ int finish_row(int nsplit, const double *__restrict__
     }
   }
   return fl;
+}
+
+// Lanes per i-particle of a split sum: one for up to 8 splits, else about a
+// quarter of the splits, at most a wave, and fewer where the i-particles
+// alone give lanes enough (ni * G at most 2^17).
+__host__ __device__ constexpr int split_lanes(int nsplit, long long ni) {
+  int G = 1;
+  if (nsplit > 8)
+    while (G < 64 && 4 * (2 * G) <= nsplit && ni * (2 * G) <= (1LL << 17)) G <<= 1;
+  return G;
+}
+
+// Lane l of a wave, in groups of G lanes per i-particle (G a power of two up
+// to 64): the wave holds w = 64 / G consecutive i-particles, lane l serving
+// i-particle l mod w as member g = l / w of its group; the members of a
+// group sit w lanes apart.
+__device__ __forceinline__ void split_lane_map(int lane, int G, int &ioff, int &g, int &xs) {
+  xs = 64 / G;
+  ioff = lane & (xs - 1);
+  g = lane / xs;
 }
 
 // ---------------------------------------------- neighbour-list overflow

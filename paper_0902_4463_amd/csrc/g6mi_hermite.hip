@@ -2,12 +2,15 @@
 // client side of the paper's CPU/GPU split, Sec. 2 and 2.1, moved onto the
 // GPU): one block step is
 //
-//   hs_min_kernel      next block time t_b = min_k (t_k + dt_k)
 //   hs_select_kernel   the particles with t_k + dt_k = t_b, predicted to t_b
 //                      in float64 (Eq. (1)-(2) with the particle's own
-//                      a and jerk); the last workgroup writes the one-cluster
-//                      descriptor that the batched force launch reads
-//   batch_plan_kernel, batch_kernel   forces on the block (g6mi_batch.hip)
+//                      a and jerk); t_b = min_k (t_k + dt_k) was gathered by
+//                      the previous step: the others' times here, the
+//                      corrected ones' in hs_correct_kernel
+//   hs_publish_kernel  the one-cluster descriptor that the batched force
+//                      launch reads
+//   batch_plan_kernel, batch_kernel, batch_reduce_kernel
+//                      forces on the block (g6mi_batch.hip)
 //   hs_correct_kernel  Hermite corrector, Aarseth time step, power-of-two
 //                      block quantisation; the corrected particle is written
 //                      back into the j-memory (its a/2 and jerk/6 too)
@@ -33,19 +36,21 @@ __device__ __forceinline__ double key_value(unsigned long long k) {
 }
 constexpr unsigned long long kKeyInf = 0xfff0000000000000ull; // order_key(+inf)
 
-__global__ __launch_bounds__(256) void hs_min_kernel(HermiteArgs h) {
-  __shared__ double s_min[256];
-  const int tid = threadIdx.x;
-  const int k = blockIdx.x * 256 + tid;
-  s_min[tid] = k < h.n ? h.jm.t[k] + h.dt[k] : INFINITY;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (tid < off) s_min[tid] = fmin(s_min[tid], s_min[tid + off]);
-    __syncthreads();
+// Workgroup minimum of one key per thread, folded into *dst with one
+// atomic (none when every key is +inf).  Every thread must call it.
+__device__ __forceinline__ void key_min(unsigned long long key, unsigned long long *dst) {
+  __shared__ unsigned long long s_key[4];
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(key, off);
+    key = o < key ? o : key;
   }
-  if (tid == 0) {
-    atomicMin(&h.ctl->tnext_key, order_key(s_min[0]));
-    if (blockIdx.x == 0) h.ctl->ni_count = 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) s_key[wave] = key;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long m = s_key[0];
+    for (int w = 1; w < static_cast<int>(blockDim.x >> 6); ++w) m = s_key[w] < m ? s_key[w] : m;
+    if (m != kKeyInf) atomicMin(dst, m);
   }
 }
 
@@ -65,13 +70,17 @@ __device__ __forceinline__ void predict_particle(const HermiteArgs &h, int k, do
 }
 
 __global__ __launch_bounds__(256) void hs_select_kernel(HermiteArgs h) {
-  __shared__ int s_wave[4], s_base, s_last;
+  __shared__ int s_wave[4], s_base;
   const int tid = threadIdx.x;
   const int k = blockIdx.x * 256 + tid;
   HermiteCtl *ctl = h.ctl;
-  const double tb = key_value(ctl->tnext_key);
+  const int ph = ctl->phase;
+  const double tb = key_value(ctl->key[ph]);
   const bool go = tb <= ctl->t_end;
-  const bool act = go && k < h.n && h.jm.t[k] + h.dt[k] == tb;
+  const double tn = k < h.n ? h.jm.t[k] + h.dt[k] : INFINITY;
+  const bool act = go && k < h.n && tn == tb;
+  // the next block time, first part: the particles this step leaves alone
+  key_min(act ? kKeyInf : order_key(tn), &ctl->key[ph ^ 1]);
   // slots of this block's active particles: wave counts, one atomic per block
   const unsigned long long m = __ballot(act);
   const int lane = tid & 63, wave = tid >> 6;
@@ -94,24 +103,34 @@ __global__ __launch_bounds__(256) void hs_select_kernel(HermiteArgs h) {
     }
     h.h2i[q] = h.h2;
   }
-  // the last workgroup to finish publishes the block as a descriptor
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) s_last = atomicAdd(&ctl->blocks_done, 1) == static_cast<int>(gridDim.x) - 1;
-  __syncthreads();
-  if (s_last && tid == 0) {
-    __threadfence();
-    g6mi_cluster d;
-    d.joff = 0;
-    d.nj = h.n;
-    d.ioff = 0;
-    d.ni = go ? ctl->ni_count : 0;
-    d.ti = go ? tb : ctl->time;
-    d.eps2 = h.eps2;
-    ctl->desc = d;
-    ctl->blocks_done = 0;
-    ctl->done = go ? 0 : 1;
-  }
+}
+
+// The block as a one-cluster descriptor for the batched force launch, or an
+// empty block once t_b > t_end, so that replays past the end change nothing;
+// then the block-time keys turn over (see HermiteCtl).
+// A launch of its own after the selection: a last-workgroup hand-over inside
+// it would need a device-scope fence per workgroup, which on gfx950 writes
+// back and invalidates the XCD's whole L2.
+__global__ __launch_bounds__(64) void hs_publish_kernel(HermiteArgs h) {
+  if (threadIdx.x != 0) return;
+  HermiteCtl *ctl = h.ctl;
+  const int ph = ctl->phase;
+  const double tb = key_value(ctl->key[ph]);
+  const bool go = tb <= ctl->t_end;
+  g6mi_cluster d;
+  d.joff = 0;
+  d.nj = h.n;
+  d.ioff = 0;
+  d.ni = go ? ctl->ni_count : 0;
+  d.ti = go ? tb : ctl->time;
+  d.eps2 = h.eps2;
+  ctl->desc = d;
+  ctl->done = go ? 0 : 1;
+  // the corrector adds the block's new times to key[ph ^ 1]; the next
+  // selection reads it and fills key[ph] afresh
+  ctl->ni_count = 0;
+  ctl->key[ph] = kKeyInf;
+  ctl->phase = ph ^ 1;
 }
 
 __device__ __forceinline__ double norm3(const double *a) {
@@ -128,25 +147,13 @@ __device__ __forceinline__ double quantise(double dt, double dt_min, double dt_m
   return ldexp(1.0, e - 1);
 }
 
-// Corrector (Makino & Aarseth 1992) for the block's particles, then the
-// Aarseth criterion with the second derivative at the end of the step, and
-// the block rule: halve while too long, double only when the time is a
-// multiple of the doubled step.
-__global__ __launch_bounds__(256) void hs_correct_kernel(HermiteArgs h) {
+// Corrector (Makino & Aarseth 1992) for block position q at block time tb,
+// then the Aarseth criterion with the second derivative at the end of the
+// step, and the block rule: halve while too long, double only when the time
+// is a multiple of the doubled step.  Returns the new step.
+__device__ __forceinline__ double correct_particle(const HermiteArgs &h, int q, double tb) {
 #pragma clang fp contract(off)
   HermiteCtl *ctl = h.ctl;
-  const int ni = ctl->desc.ni;
-  const double tb = ctl->desc.ti;
-  const int q = blockIdx.x * 256 + threadIdx.x;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctl->tnext_key = kKeyInf;
-    if (ni > 0) {
-      ctl->block_steps += 1;
-      ctl->particle_steps += ni;
-      ctl->time = tb;
-    }
-  }
-  if (q >= ni) return;
   const int k = h.active[q];
   const size_t cap = h.jm.cap;
   const double dt = tb - h.jm.t[k];
@@ -196,20 +203,33 @@ __global__ __launch_bounds__(256) void hs_correct_kernel(HermiteArgs h) {
   h.dt[k] = nw;
   h.pot[k] = h.pot1[q];
   if (!finite) atomicOr(&ctl->flags, 1);
+  return nw;
 }
 
-// First force evaluation of every particle at the common start time: a,
-// jerk and potential stored, first step eta_s |a| / |jerk| quantised.
-__global__ __launch_bounds__(256) void hs_start_kernel(HermiteArgs h) {
-#pragma clang fp contract(off)
+// The block's particles corrected (correct_particle, one thread each) and
+// the minimum of their new t + dt folded into the next block time.
+__global__ __launch_bounds__(256) void hs_correct_kernel(HermiteArgs h) {
   HermiteCtl *ctl = h.ctl;
   const int ni = ctl->desc.ni;
+  const double tb = ctl->desc.ti;
   const int q = blockIdx.x * 256 + threadIdx.x;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctl->tnext_key = kKeyInf;
-    ctl->time = ctl->desc.ti;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && ni > 0) {
+    ctl->block_steps += 1;
+    ctl->particle_steps += ni;
+    ctl->time = tb;
   }
-  if (q >= ni) return;
+  if (blockIdx.x * 256 >= ni) return; // whole workgroups past the block
+  unsigned long long next = kKeyInf;
+  if (q < ni) next = order_key(tb + correct_particle(h, q, tb));
+  // the next block time, second part: this block's particles
+  key_min(next, &ctl->key[ctl->phase]);
+}
+
+// First step of block position q: a, jerk and potential stored, the step
+// eta_s |a| / |jerk| quantised.  Returns the step.
+__device__ __forceinline__ double start_particle(const HermiteArgs &h, int q) {
+#pragma clang fp contract(off)
+  HermiteCtl *ctl = h.ctl;
   const int k = h.active[q];
   const size_t cap = h.jm.cap;
   double a1[3], j1[3];
@@ -224,9 +244,23 @@ __global__ __launch_bounds__(256) void hs_start_kernel(HermiteArgs h) {
     h.jm.j6[d * cap + k] = j1[d] / 6.0;
   }
   const double dt = h.eta_s * norm3(a1) / fmax(norm3(j1), 1e-300);
-  h.dt[k] = quantise(dt, h.dt_min, h.dt_max);
+  const double step = quantise(dt, h.dt_min, h.dt_max);
+  h.dt[k] = step;
   h.pot[k] = h.pot1[q];
   if (!finite) atomicOr(&ctl->flags, 1);
+  return step;
+}
+
+// First force evaluation of every particle at the common start time
+// (start_particle, one thread each) and the first next block time.
+__global__ __launch_bounds__(256) void hs_start_kernel(HermiteArgs h) {
+  HermiteCtl *ctl = h.ctl;
+  const int ni = ctl->desc.ni;
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->time = ctl->desc.ti;
+  if (blockIdx.x * 256 >= ni) return; // whole workgroups past the block
+  const double dt = q < ni ? start_particle(h, q) : INFINITY;
+  key_min(q < ni ? order_key(ctl->desc.ti + dt) : kKeyInf, &ctl->key[ctl->phase]);
 }
 
 // Clear the step state before the first force evaluation: every particle
@@ -234,8 +268,6 @@ __global__ __launch_bounds__(256) void hs_start_kernel(HermiteArgs h) {
 __global__ __launch_bounds__(256) void hs_reset_kernel(HermiteArgs h) {
   const int k = blockIdx.x * 256 + threadIdx.x;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    h.ctl->tnext_key = kKeyInf;
-    h.ctl->blocks_done = 0;
     h.ctl->flags = 0;
     h.ctl->done = 0;
     h.ctl->block_steps = 0;
@@ -261,8 +293,8 @@ hipError_t launch_hs_reset(const HermiteArgs &h, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t launch_hs_select(const HermiteArgs &h, hipStream_t s) {
-  hipLaunchKernelGGL(hs_min_kernel, grid_n(h.n), dim3(256), 0, s, h);
   hipLaunchKernelGGL(hs_select_kernel, grid_n(h.n), dim3(256), 0, s, h);
+  hipLaunchKernelGGL(hs_publish_kernel, dim3(1), dim3(64), 0, s, h);
   return hipGetLastError();
 }
 hipError_t launch_hs_correct(const HermiteArgs &h, bool start, hipStream_t s) {

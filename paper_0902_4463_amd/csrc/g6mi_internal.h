@@ -81,7 +81,9 @@ hipError_t launch_predict(int prec, int nj, double ti, const JMem &jm,
 hipError_t launch_force(int prec, bool nbl, const ForceArgs &a, int nsplit,
                         hipStream_t s);
 
-hipError_t launch_reduce(int nsplit, int ni, const double *part,
+// iperm: row of the partials at each position (spatially ordered blocks),
+// or null where partials sit at their own rows.
+hipError_t launch_reduce(int nsplit, int ni, const int *iperm, const double *part,
                          const double *nn_r2, const int *nn_slot,
                          const int *jindex, int *nb_count, int *nb_slot,
                          bool nbl, double *acc, double *jerk, double *pot,
@@ -118,25 +120,40 @@ struct SpatialBufs {
   int *inv = nullptr;                            // [nj] sorted position of each slot
   float4 *sorted = nullptr;                      // [nj][3] DS records in sorted order
   float4 *tinfo = nullptr;                       // [ntiles][4] centre, radius, box
+  double *sxi = nullptr, *svi = nullptr;         // [ni][3] i-state in sorted order
+  double *sh2 = nullptr;                         // [ni]
+  int *sislot = nullptr;                         // [ni]
+  int *spos = nullptr;                           // [ni] sorted position of the i-particle's own record, or -1
   void *temp = nullptr;                          // radix-sort scratch
   size_t temp_bytes = 0;
 };
 
 struct SpatialArgs {
   const int *iperm = nullptr;
-  const int *inv = nullptr;
+  const int *spos = nullptr;
   const float4 *tinfo = nullptr;
 };
 
 // Scratch bytes of a radix sort of n (key, index) pairs.
 hipError_t spatial_sort_bytes(int n, size_t *bytes);
-// Box, keys, sorts of j and i, sorted records and tile table.
+// Box, keys, sorts of j and i, sorted records, tile table and the i-state
+// gathered into sorted order.
 hipError_t launch_spatial_prep(const SpatialBufs &b, int nj, int ni, const void *jpred, const double *xi,
-                               hipStream_t s);
-// The DS interaction over sorted records (a.jpred = b.sorted); i-blocks of 512.
+                               const double *vi, const double *h2, const int *islot, hipStream_t s);
+// The DS interaction over b.sorted and the sorted i-state (a holds the
+// unsorted arrays); i-blocks of 512; partials at sorted positions (reduce
+// with iperm = b.iperm).
 hipError_t launch_force_spatial(bool nbl, const ForceArgs &a, const SpatialBufs &b, int nsplit, hipStream_t s);
 
 // ------------------------------------------ batched multi-cluster launch
+
+// Smallest i-block the batch plan uses when it cuts a cluster's block into
+// more i-blocks for occupancy; bounds the work items at
+// (ni_total / kBatchMinIpw + clusters + 1) * max_split.
+#ifndef G6MI_BATCH_MIN_IPW
+#define G6MI_BATCH_MIN_IPW 32
+#endif
+constexpr int kBatchMinIpw = G6MI_BATCH_MIN_IPW;
 
 // Launch policy of a batch (see BatchPlan): item_work = work per item in
 // units of one tile x 512 i-particles, wide_min = smallest cluster block
@@ -149,12 +166,13 @@ struct BatchTune {
 };
 
 // Per-cluster plan written by the plan kernel: i-particles per workgroup
-// (512 = two per lane), j-splits and tiles per split, i-blocks, and the
-// cluster's first i-block counter, first work item and first partial entry.
+// (512 = two per lane), j-splits and tiles per split, i-blocks, the
+// cluster's first i-block counter, first work item and first partial entry,
+// and its block size (0 for a skipped cluster).
 // Its work items are item0 .. item0 + nib * nsplit - 1, item item0 + r
 // being i-block r / nsplit, j-split r % nsplit.
 struct BatchPlan {
-  int ipw, log2ipw, nsplit, per, nib, ib0, item0, pad;
+  int ipw, log2ipw, nsplit, per, nib, ib0, item0, ni;
   long long pbase;
 };
 
@@ -177,7 +195,7 @@ struct BatchArgs {
   double *nn_r2 = nullptr; // [pcap]
   int *nn_slot = nullptr;  // [pcap]
   size_t pcap = 0;
-  int *ibcnt = nullptr;    // [ni_total] finished splits per i-block
+  int *ib_cl = nullptr;    // [ni_total] cluster of each i-block (at most one per row)
   int nbl = 1;
   double *acc = nullptr, *jerk = nullptr, *pot = nullptr, *r2nn = nullptr;
   int *nnb = nullptr, *status = nullptr, *ovf_list = nullptr, *ovf_tag = nullptr;
@@ -197,10 +215,16 @@ constexpr int kFlagBadCluster = 4;
 // ------------------------------------------ device-resident block steps
 
 // Control block of the device-resident Hermite integrator (device memory).
+//
+// Block times as order keys (the minimum over the grid is one atomicMin):
+// key[phase] holds this step's block time t_b; key[phase ^ 1] gathers the
+// next one, the minimum of t + dt over the particles the selection leaves
+// alone and over the corrected ones.  The publish launch between the two
+// clears key[phase] and flips phase.
 struct HermiteCtl {
-  unsigned long long tnext_key; // order key of the next block time (+inf between steps)
+  unsigned long long key[2];
+  int phase;
   int ni_count;                 // particles selected so far in this step
-  int blocks_done;              // finished workgroups of the select launch
   int done;                     // 1: no particle is due at or before t_end
   int flags;                    // bit 0: a non-finite force
   long long block_steps, particle_steps;

@@ -106,6 +106,34 @@ __global__ __launch_bounds__(kWG, wide_waves<PREC>()) void force_wide(ForceArgs 
   if (w.v1) store(i1, w.t1, w.ebest1, w.eslot1);
 }
 
+// K float4 per lane of a tile of n4 float4 (lane tid holds elements tid,
+// tid + 256, ...), in named registers of a plain vector type (an aggregate
+// float4 copy would go through the stack).  Loads are clamped to the last
+// element so that every lane loads unconditionally; the store writes only
+// the elements below n4.
+template <int K> struct TileRegs {
+  static_assert(K >= 1 && K <= 4, "one to four float4 per lane");
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  v4 v0, v1, v2, v3;
+  __device__ __forceinline__ void load(const float4 *__restrict__ src4, int tid, int n4) {
+    const v4 *src = reinterpret_cast<const v4 *>(src4);
+    v0 = src[min(tid, n4 - 1)];
+    if constexpr (K > 1) v1 = src[min(kWG + tid, n4 - 1)];
+    if constexpr (K > 2) v2 = src[min(2 * kWG + tid, n4 - 1)];
+    if constexpr (K > 3) v3 = src[min(3 * kWG + tid, n4 - 1)];
+  }
+  __device__ __forceinline__ void store(float4 *__restrict__ dst4, int tid, int n4) const {
+    v4 *dst = reinterpret_cast<v4 *>(dst4);
+    if (tid < n4) dst[tid] = v0;
+    if constexpr (K > 1)
+      if (kWG + tid < n4) dst[kWG + tid] = v1;
+    if constexpr (K > 2)
+      if (2 * kWG + tid < n4) dst[2 * kWG + tid] = v2;
+    if constexpr (K > 3)
+      if (3 * kWG + tid < n4) dst[3 * kWG + tid] = v3;
+  }
+};
+
 // Small blocks (NarrowLane): ipw i-particles per workgroup (a power of two,
 // at most 256) and L = 256 / ipw lanes per i-particle; lane tid handles
 // i-particle (tid mod ipw) and the records sub, sub + L, ... of every tile,
@@ -133,18 +161,19 @@ __global__ __launch_bounds__(kWG) void force_kernel(ForceArgs a) {
   const int te = min(ntiles, tb + per);
   const float4 *jp = static_cast<const float4 *>(a.jpred);
 
+  // The next tile's records are loaded into registers while the current
+  // one is evaluated: a block of few i-particles spends little time per
+  // tile, too little to cover the load on its own.
+  TileRegs<kLoads> nxt;
+  if (tb < te) nxt.load(jp + static_cast<size_t>(tb) * kTile * REC, tid, min(kTile, a.nj - tb * kTile) * REC);
   for (int tt = tb; tt < te; ++tt) {
     const int jbase = tt * kTile;
     const int cnt = min(kTile, a.nj - jbase);
     __syncthreads();
+    nxt.store(tile, tid, cnt * REC);
     {
-      const float4 *src = jp + static_cast<size_t>(jbase) * REC;
-      const int n4 = cnt * REC;
-#pragma unroll
-      for (int q = 0; q < kLoads; ++q) {
-        const int idx = q * kWG + tid;
-        if (idx < n4) tile[idx] = src[idx];
-      }
+      const int tn = min(tt + 1, te - 1); // the last tile loads itself again
+      nxt.load(jp + static_cast<size_t>(tn) * kTile * REC, tid, min(kTile, a.nj - tn * kTile) * REC);
     }
     __syncthreads();
     n.tile(tile, jbase, cnt, eps2, a.nb_count, a.nb_slot);
@@ -170,22 +199,34 @@ __global__ __launch_bounds__(kWG) void force_kernel(ForceArgs a) {
 
 // --------------------------------------------------------------- reduction
 
-// One thread per i-particle (finish_row): float64 sum over the j-splits in
-// split order, nearest-neighbour minimum, neighbour-list finalisation.
+// 2^log2G lanes per i-particle (split_sum, then finish_out on the first
+// lane), laid out by split_lane_map: float64 sum over the j-splits in a fixed
+// order, nearest-neighbour minimum, neighbour-list finalisation.  The
+// partials of position i belong to row iperm[i] when iperm is given (the
+// spatially ordered kernel writes them in sorted order), else to row i.
 // status[kStatusFlags] bit 0: a non-finite output; bit 1: a neighbour list
 // overflowed (those i-particles are queued in ovf_list for nb_exact_kernel).
 __global__ __launch_bounds__(256) void reduce_kernel(
-    int nsplit, int ni, const double *__restrict__ part,
+    int nsplit, int ni, int log2G, const int *__restrict__ iperm, const double *__restrict__ part,
     const double *__restrict__ nn_r2, const int *__restrict__ nn_slot,
     const int *__restrict__ jindex, const int *__restrict__ nb_count,
     int *__restrict__ nb_slot, int nbl, double *__restrict__ acc,
     double *__restrict__ jerk, double *__restrict__ pot, int *__restrict__ nnb,
     double *__restrict__ r2nn, int *__restrict__ status, int *__restrict__ ovf_list) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= ni) return;
+  const long long t = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
+  const int G = 1 << log2G;
+  int ioff, g, xs;
+  split_lane_map(static_cast<int>(t & 63), G, ioff, g, xs);
+  const long long i = (t >> 6) * xs + ioff;
+  if (i >= ni) return; // whole groups: the G lanes of an i-particle share i
   const size_t n = static_cast<size_t>(ni);
-  const int fl = finish_row(nsplit, part + i, 7 * n, n, nn_r2 + i, nn_slot + i, n, i, jindex, nb_count,
-                            nb_slot, nbl != 0, acc, jerk, pot, nnb, r2nn, status, ovf_list, nullptr, 0);
+  double sum[7], best;
+  int bslot;
+  split_sum(nsplit, G, g, xs, part + i, 7 * n, n, nn_r2 + i, nn_slot + i, n, sum, best, bslot);
+  if (g != 0) return;
+  const int row = iperm ? iperm[i] : static_cast<int>(i);
+  const int fl = finish_out(sum, best, bslot, row, jindex, nb_count, nb_slot, nbl != 0, acc, jerk, pot, nnb, r2nn,
+                            status, ovf_list, nullptr, 0);
   if (fl) atomicOr(status + kStatusFlags, fl);
 }
 
@@ -306,13 +347,18 @@ hipError_t launch_force(int prec, bool nbl, const ForceArgs &a, int nsplit, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(int nsplit, int ni, const double *part, const double *nn_r2,
+hipError_t launch_reduce(int nsplit, int ni, const int *iperm, const double *part, const double *nn_r2,
                          const int *nn_slot, const int *jindex, int *nb_count, int *nb_slot,
                          bool nbl, double *acc, double *jerk, double *pot, int *nnb,
                          double *r2nn, int *status, int *ovf_list, hipStream_t s) {
   if (ni <= 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(ni)), dim3(256), 0, s, nsplit, ni, part,
-                     nn_r2, nn_slot, jindex, nb_count, nb_slot, nbl ? 1 : 0, acc, jerk, pot,
+  const int G = split_lanes(nsplit, ni);
+  int log2G = 0;
+  while ((1 << log2G) < G) ++log2G;
+  const long long waves = (ni + (64 >> log2G) - 1) / (64 >> log2G);
+  const long long lanes = waves * 64;
+  hipLaunchKernelGGL(reduce_kernel, dim3(static_cast<unsigned>((lanes + 255) / 256)), dim3(256), 0, s, nsplit, ni,
+                     log2G, iperm, part, nn_r2, nn_slot, jindex, nb_count, nb_slot, nbl ? 1 : 0, acc, jerk, pot,
                      nnb, r2nn, status, ovf_list);
   return hipGetLastError();
 }

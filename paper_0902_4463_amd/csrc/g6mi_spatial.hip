@@ -73,15 +73,20 @@ __device__ __forceinline__ void box_reduce(float lo[3], float hi[3], unsigned *_
   }
 }
 
+// Grid-strided over the records: a few hundred workgroups, so that the six
+// box words take few atomics (one workgroup per 256 records serialised
+// about 25000 of them on six addresses: 0.1 ms at 2^20 records).
 __global__ __launch_bounds__(256) void sp_bbox_kernel(int nj, const float4 *__restrict__ rec,
                                                       unsigned *__restrict__ box) {
-  const int k = blockIdx.x * 256 + threadIdx.x;
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  if (k < nj) {
+  for (int k = blockIdx.x * 256 + threadIdx.x; k < nj; k += gridDim.x * 256) {
     const float4 p = rec[3 * static_cast<size_t>(k)];
-    lo[0] = hi[0] = p.x;
-    lo[1] = hi[1] = p.y;
-    lo[2] = hi[2] = p.z;
+    lo[0] = fminf(lo[0], p.x);
+    lo[1] = fminf(lo[1], p.y);
+    lo[2] = fminf(lo[2], p.z);
+    hi[0] = fmaxf(hi[0], p.x);
+    hi[1] = fmaxf(hi[1], p.y);
+    hi[2] = fmaxf(hi[2], p.z);
   }
   box_reduce(lo, hi, box);
 }
@@ -147,6 +152,31 @@ __global__ __launch_bounds__(256) void sp_gather_kernel(int nj, const int *__res
   inv[k] = p;
 }
 
+// i-state at sorted position q = that of row iperm[q], and spos[q] = the
+// sorted position of its own j-record (-1 without one): the force kernel then
+// reads its i-particles contiguously.
+__global__ __launch_bounds__(256) void sp_igather_kernel(int ni, int nj, const int *__restrict__ iperm,
+                                                         const int *__restrict__ inv,
+                                                         const double *__restrict__ xi,
+                                                         const double *__restrict__ vi,
+                                                         const double *__restrict__ h2,
+                                                         const int *__restrict__ islot, double *__restrict__ sxi,
+                                                         double *__restrict__ svi, double *__restrict__ sh2,
+                                                         int *__restrict__ sislot, int *__restrict__ spos) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= ni) return;
+  const size_t r = static_cast<size_t>(iperm[q]), d = static_cast<size_t>(q);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    sxi[3 * d + k] = xi[3 * r + k];
+    svi[3 * d + k] = vi[3 * r + k];
+  }
+  sh2[d] = h2[r];
+  const int slot = islot[r];
+  sislot[d] = slot;
+  spos[d] = (slot >= 0 && slot < nj) ? inv[slot] : -1;
+}
+
 // One workgroup per tile of sorted records: box of the hi parts, centre c
 // (float64 midpoint, split double-single), radius r_t = the largest
 // |(x_hi - c_hi) + (x_lo - c_lo)| computed as on the far path, rounded up.
@@ -201,9 +231,10 @@ __global__ __launch_bounds__(256) void sp_tile_kernel(int nj, const float4 *__re
   }
 }
 
-// The wide DS kernel over sorted records (a.jpred) and sorted i-blocks:
-// workgroup b takes the i-particles iperm[512 b + tid] and
-// iperm[512 b + 256 + tid]; partials go to their own rows as in force_wide.
+// The wide DS kernel over sorted records (a.jpred) and the sorted i-state
+// (a.xi, a.vi, a.h2, a.islot): workgroup b takes sorted positions 512 b + tid
+// and 512 b + 256 + tid; partials go to those positions, neighbour lists to
+// the i-particles' own rows iperm[q].
 template <bool NBL>
 __global__ __launch_bounds__(kWG, wide_waves<G6MI_PREC_DS>()) void force_spatial(ForceArgs a, SpatialArgs sp) {
   constexpr int REC = rec4<G6MI_PREC_DS>();
@@ -216,9 +247,11 @@ __global__ __launch_bounds__(kWG, wide_waves<G6MI_PREC_DS>()) void force_spatial
   const int q0 = blockIdx.x * (2 * kWG) + tid, q1 = q0 + kWG;
   const bool v0 = q0 < a.ni, v1 = q1 < a.ni;
   WideLanes<G6MI_PREC_DS, NBL, true> w;
-  w.init(a, v0 ? sp.iperm[q0] : 0, v1 ? sp.iperm[q1] : 0, v0, v1);
-  w.pos0 = (w.slot0 >= 0 && w.slot0 < a.nj) ? sp.inv[w.slot0] : -1;
-  w.pos1 = (w.slot1 >= 0 && w.slot1 < a.nj) ? sp.inv[w.slot1] : -1;
+  w.init(a, v0 ? q0 : 0, v1 ? q1 : 0, v0, v1);
+  w.row0 = v0 ? sp.iperm[q0] : 0;
+  w.row1 = v1 ? sp.iperm[q1] : 0;
+  w.pos0 = v0 ? sp.spos[q0] : -1;
+  w.pos1 = v1 ? sp.spos[q1] : -1;
   const float eps2 = static_cast<float>(a.eps2);
 
   // box of this workgroup's i-particles (hi parts)
@@ -317,8 +350,8 @@ __global__ __launch_bounds__(kWG, wide_waves<G6MI_PREC_DS>()) void force_spatial
     a.nn_r2[blockIdx.y * ni + i] = static_cast<double>(best);
     a.nn_slot[blockIdx.y * ni + i] = bslot;
   };
-  if (w.v0) store(w.row0, w.t0, w.ebest0, w.eslot0);
-  if (w.v1) store(w.row1, w.t1, w.ebest1, w.eslot1);
+  if (w.v0) store(q0, w.t0, w.ebest0, w.eslot0);
+  if (w.v1) store(q1, w.t1, w.ebest1, w.eslot1);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -333,10 +366,10 @@ hipError_t spatial_sort_bytes(int n, size_t *bytes) {
 }
 
 hipError_t launch_spatial_prep(const SpatialBufs &b, int nj, int ni, const void *jpred, const double *xi,
-                               hipStream_t s) {
+                               const double *vi, const double *h2, const int *islot, hipStream_t s) {
   const float4 *rec = static_cast<const float4 *>(jpred);
   hipLaunchKernelGGL(sp_init_kernel, dim3(1), dim3(64), 0, s, b.box);
-  hipLaunchKernelGGL(sp_bbox_kernel, dim3(blocks256(nj)), dim3(256), 0, s, nj, rec, b.box);
+  hipLaunchKernelGGL(sp_bbox_kernel, dim3(std::min(blocks256(nj), 512u)), dim3(256), 0, s, nj, rec, b.box);
   hipLaunchKernelGGL(sp_jkeys_kernel, dim3(blocks256(nj)), dim3(256), 0, s, nj, rec, b.box, b.keys_in, b.vals_in);
   size_t bytes = b.temp_bytes;
   hipError_t e = rocprim::radix_sort_pairs(b.temp, bytes, b.keys_in, b.keys_out, b.vals_in, b.jperm,
@@ -350,20 +383,28 @@ hipError_t launch_spatial_prep(const SpatialBufs &b, int nj, int ni, const void 
   e = rocprim::radix_sort_pairs(b.temp, bytes, b.keys_in, b.keys_out, b.vals_in, b.iperm, static_cast<size_t>(ni),
                                 0, 30, s);
   if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sp_igather_kernel, dim3(blocks256(ni)), dim3(256), 0, s, ni, nj, b.iperm, b.inv, xi, vi, h2,
+                     islot, b.sxi, b.svi, b.sh2, b.sislot, b.spos);
   return hipGetLastError();
 }
 
 hipError_t launch_force_spatial(bool nbl, const ForceArgs &a, const SpatialBufs &b, int nsplit, hipStream_t s) {
   if (a.ni <= 0) return hipSuccess;
+  ForceArgs as = a; // sorted records and i-state
+  as.jpred = b.sorted;
+  as.xi = b.sxi;
+  as.vi = b.svi;
+  as.h2 = b.sh2;
+  as.islot = b.sislot;
   SpatialArgs sp;
   sp.iperm = b.iperm;
-  sp.inv = b.inv;
+  sp.spos = b.spos;
   sp.tinfo = b.tinfo;
   const dim3 grid(static_cast<unsigned>((a.ni + 2 * kWG - 1) / (2 * kWG)), static_cast<unsigned>(nsplit));
   if (nbl)
-    hipLaunchKernelGGL(force_spatial<true>, grid, dim3(kWG), 0, s, a, sp);
+    hipLaunchKernelGGL(force_spatial<true>, grid, dim3(kWG), 0, s, as, sp);
   else
-    hipLaunchKernelGGL(force_spatial<false>, grid, dim3(kWG), 0, s, a, sp);
+    hipLaunchKernelGGL(force_spatial<false>, grid, dim3(kWG), 0, s, as, sp);
   return hipGetLastError();
 }
 

@@ -223,8 +223,11 @@ def test_batch_launch_policies(g6, sess, tuning):
 def test_batch_equals_separate_calls(g6, sess):
     """A cluster's rows in a batch agree with a separate single-system call
     on that cluster alone: identical nearest neighbours and neighbour lists
-    (the same float32 arithmetic on the same records) and forces equal up to
-    the order of float64 additions over j-splits."""
+    (the same float32 pair arithmetic on the same records) and forces equal
+    up to summation order.  The batch may cut a small block into smaller
+    i-blocks than the single call, with more lanes per i-particle, so the
+    float32 partial sums differ in order: 1e-6 relative for acceleration and
+    potential, 1e-5 for jerk."""
     import torch
     cb, xp, vp, xi, vi, h2, ref = small_case()
     sess.load(cb.jm)
@@ -254,10 +257,10 @@ def test_batch_equals_separate_calls(g6, sess):
                                                  b.h2[a0:a1], *out))
             torch.cuda.synchronize()
             acc, jerk, pot, nnb, r2nn = (t.cpu().numpy() for t in out)
-            for name, x, y in (("acc", acc, gpu["acc"][a0:a1]), ("jerk", jerk, gpu["jerk"][a0:a1])):
+            for name, x, y, tol in (("acc", acc, gpu["acc"][a0:a1], 1e-6), ("jerk", jerk, gpu["jerk"][a0:a1], 1e-5)):
                 err = np.linalg.norm(x - y, axis=1) / np.maximum(np.linalg.norm(x, axis=1), 1e-300)
-                assert err.max() <= 1e-13, (c, name, err.max())
-            assert np.all(np.abs(pot - gpu["pot"][a0:a1]) <= 1e-13 * np.abs(pot))
+                assert err.max() <= tol, (c, name, err.max())
+            assert np.all(np.abs(pot - gpu["pot"][a0:a1]) <= 1e-6 * np.abs(pot))
             assert np.array_equal(nnb, gpu["nn_index"][a0:a1]), c
             assert np.array_equal(r2nn, gpu["nn_r2"][a0:a1]), c
             assert g6.g6_read_neighbour_list(one.id) in (0, 1)

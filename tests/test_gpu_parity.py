@@ -144,6 +144,26 @@ def test_launch_shapes(g6, orc, sess, shape):
         assert np.array_equal(a[key], b[key]), key
 
 
+@pytest.mark.parametrize("prec", ["ds", "fp64"])
+@pytest.mark.parametrize("shape", [(1, 79), (4, 37), (16, 64), (256, 9), (32, 17)])
+def test_split_sums_over_lane_groups(g6, orc, sess, prec, shape):
+    """Many j-splits of few i-particles: the reduction adds each
+    i-particle's splits over a group of lanes (4..64 lanes, ragged split
+    counts per lane) and still meets the tolerance, with identical bits on a
+    repeated call and the same nearest neighbours as the oracle."""
+    jm = workloads.random_cluster(20000, seed=81)
+    slots = workloads.active_set(20000, 45, seed=6)
+    eps2, h2 = 1e-4, 0.01
+    ref = with_xp(orc, jm, oracle_eval(orc, jm, slots, eps2, h2))
+    sess.load(jm)
+    a = gpu_eval(sess, g6, jm, slots, ref, eps2, h2, prec, shape)
+    assert g6.g6mi_get_shape(sess.id)["j_splits"] == shape[1]
+    assert_parity(a, ref, jm, h2, prec, f"splits shape={shape}")
+    b = gpu_eval(sess, g6, jm, slots, ref, eps2, h2, prec, shape)
+    for key in ("acc", "jerk", "pot", "nn_index", "nn_r2", "nb_count", "nb_list"):
+        assert np.array_equal(a[key], b[key]), key
+
+
 def test_i_particles_outside_jmemory(g6, orc, sess):
     """i-particles whose index is not stored in the j-memory feel every
     j-particle (no self exclusion)."""
