@@ -4,7 +4,7 @@ against N (the paper's accuracy and block-size measurements, Sec. 3.2,
 Fig. devseta and Fig. block), with the block steps run inside the library
 (g6mi_hermite_*).
 
-    python -m hermite.study --n 32768 131072 --eta 0.003 0.01 0.03 0.1 \\
+    python -m hermite.study --n 32768 131072 --eta 1e-4 3e-4 1e-3 3e-3 0.01 0.03 0.1 0.3 \\
         --precision ds fp64 --t-end 0.25 > study.jsonl
 
 Each run: equal-mass Plummer sphere (seeded, Henon units), softening 1e-4,
@@ -82,7 +82,7 @@ def run_one(g6, hid, jm, eta, prec, t_end, dt_max, max_steps):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--n", type=int, nargs="+", default=[32768, 131072])
-    ap.add_argument("--eta", type=float, nargs="+", default=[0.003, 0.01, 0.03, 0.1])
+    ap.add_argument("--eta", type=float, nargs="+", default=[1e-4, 3e-4, 1e-3, 3e-3, 0.01, 0.03, 0.1, 0.3])
     ap.add_argument("--precision", nargs="+", default=["ds", "fp64"], choices=["ds", "fp32", "fp64"])
     ap.add_argument("--t-end", type=float, default=0.25)
     ap.add_argument("--dt-max", type=float, default=2.0 ** -4)

@@ -523,3 +523,29 @@ def test_spatial_order_parity(g6, orc, sess, n, ni):
     nn = parity.nn_report(sp["nn_index"], plain["nn_index"], parity.r2_to(xp, jm.index, ref["xi"], np.arange(len(slots)),
                                                                            plain["nn_index"]), xp, jm.index, ref["xi"])
     assert nn["ok"], nn
+
+
+def test_spatial_order_neighbour_overflow(g6, orc, sess):
+    """Morton ordering forced on with every list overflowing and a shuffled
+    index column: partials sit at sorted positions and are mapped back to
+    their rows, so the overflow queue must still name rows, and the exact
+    pass must keep the 256 smallest indices as the oracle does."""
+    rng = np.random.default_rng(62)
+    n = 3000
+    x = rng.normal(size=(n, 3)) * 0.01
+    jm = workloads.make_jmemory(x, rng.normal(size=(n, 3)), np.full(n, 1 / n), meta=dict(ti=0.0),
+                                index=rng.permutation(n) * 3 + 7)
+    slots = rng.permutation(n)[:900]
+    ref = with_xp(orc, jm, oracle_eval(orc, jm, slots, 1e-6, 1.0))
+    sess.load(jm)
+    try:
+        g6.check(sess.id, g6.g6mi_set_spatial(sess.id, 2))
+        gpu = gpu_eval(sess, g6, jm, slots, ref, 1e-6, 1.0, "ds")
+    finally:
+        g6.g6mi_set_spatial(sess.id, 1)
+    assert gpu["nb_overflow"]
+    assert np.array_equal(gpu["nb_count"], ref["nb_count"])
+    assert np.array_equal(gpu["nb_list"], ref["nb_list"])
+    forces = {k: v for k, v in gpu.items() if k not in ("nb_count", "nb_list")}
+    assert_parity(forces, ref, jm, 1.0, "ds", "spatial overflow")
+
