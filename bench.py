@@ -83,6 +83,10 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-cluster workload")
     ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--tune-cache", default=None, help="tuning cache file of the batched launch")
+    ap.add_argument("--batched-tuning", default=None,
+                    help="item_work,wide_min,wg_per_cu,max_split for the batched launch instead of autotuning")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched workload; prints its record as the JSON line (a diagnostic mode)")
     return ap.parse_args()
 
 
@@ -117,9 +121,14 @@ def batched_bench(args, g6, torch, dev):
     cl = g6.clusters(cb.joff[:-1], nj, cb.ioff[:-1], ni_c, cb.ti, cb.eps2)
     stream = torch.cuda.Stream()
     args_dev = (islot, xi, vi, h2, *out)
-    with torch.cuda.stream(stream):
-        rc, tuning = g6.g6mi_batch_autotune(hid, cl, n_i, *args_dev, stream=stream, cache_path=args.tune_cache)
-        g6.check(hid, rc)
+    if args.batched_tuning:
+        iw, wm, wg, ms = (int(q) for q in args.batched_tuning.split(","))
+        g6.check(hid, g6.g6mi_batch_set_tuning(hid, dict(item_work=iw, wide_min=wm, wg_per_cu=wg, max_split=ms)))
+        tuning = g6.g6mi_batch_get_tuning(hid)
+    else:
+        with torch.cuda.stream(stream):
+            rc, tuning = g6.g6mi_batch_autotune(hid, cl, n_i, *args_dev, stream=stream, cache_path=args.tune_cache)
+            g6.check(hid, rc)
     torch.cuda.synchronize()
     log(f"[bench] batched tuning {tuning}")
 
@@ -215,6 +224,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.batched_only:
+        print(json.dumps(dict(mode="batched_only", batched=batched_bench(args, g6, torch, dev))), flush=True)
+        return
     n = 2 ** args.log2n
     log(f"[bench] generating Plummer/Salpeter N={n}")
     jm = workloads.config_c3(n=n)

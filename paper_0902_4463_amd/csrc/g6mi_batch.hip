@@ -71,8 +71,10 @@ __device__ __forceinline__ int first_above(const int *inc, int q) {
 // batch of few or small clusters still spreads over the GPU.
 //
 // Pass 1 checks the descriptors, picks the block shape of each cluster
-// (kept in its plan entry) and adds up the batch's work; pass 2 picks the
-// splits and scans items, i-blocks and partial entries.
+// (kept in its plan entry) and adds up the batch's work; pass 1b cuts the
+// blocks of clusters too small to fill their share of the GPU; pass 2 picks
+// the splits, scans items, i-blocks and partial entries, and fills the
+// item -> cluster and i-block -> cluster tables.
 __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
   const int tid = threadIdx.x;
   if (blockIdx.x > 0) {
