@@ -359,8 +359,10 @@ int g6mi_batch_calc_device(int id, int ncl, const g6mi_cluster *d_cl,
 int g6mi_batch_use_graph(int id, int on);
 
 /* Launch policy of batched calls.
- *   item_work  work per item, in units of one j-tile of 256 records
- *              against 512 i-particles (1 .. 1024; default 2)
+ *   item_work  work per item, in units of a quarter of one j-tile of 256
+ *              records against 512 i-particles (1 .. 1024; default 8); a
+ *              block below wide_min is also cut into i-blocks of at most
+ *              item_work * 128 particles
  *   wide_min   clusters with at least this many i-particles use two
  *              i-particles per lane (default 512)
  *   wg_per_cu  persistent workgroups per compute unit (0: the kernel's
@@ -384,10 +386,11 @@ int g6mi_batch_get_tuning(int id, g6mi_batch_tuning *t);
  * size classes of the batch's pairs, i-particles and j-slots.  When the
  * key is in this process's table or in the text file cache_path (or the
  * file named by the environment variable G6MI_TUNE_CACHE when cache_path is
- * NULL; lines "g6mi-batch-tune-v1 key item_work wide_min wg_per_cu
+ * NULL; lines "g6mi-batch-tune-v2 key item_work wide_min wg_per_cu
  * max_split ms", the last line for a key wins) that policy is applied.
- * Otherwise every combination of item_work 1, 2, 4, 8, 16, wide_min 257,
- * 512, 1024 and wg_per_cu 1 .. occupancy is timed on this batch (one
+ * Otherwise every combination of item_work 1, 2, 4, 8, 16, 32, 64,
+ * wide_min 257, 512, 1024, 2^30 and wg_per_cu 1 .. occupancy is timed on
+ * this batch (one
  * untimed and `reps` timed runs each, reps <= 0 meaning 3; the output
  * arrays are overwritten), the fastest is applied and appended to the file.
  * The chosen policy is written to *best when best is not NULL.  Returns 0,

@@ -1351,7 +1351,7 @@ g6mi_batch_tuning current_tuning(const Handle &h) {
 std::mutex g_tune_mu;
 std::unordered_map<std::string, g6mi_batch_tuning> g_tune;
 
-constexpr const char *kTuneTag = "g6mi-batch-tune-v1";
+constexpr const char *kTuneTag = "g6mi-batch-tune-v2";
 
 int ilog2_floor(double v) { return v >= 1.0 ? static_cast<int>(std::floor(std::log2(v))) : -1; }
 
@@ -1464,8 +1464,8 @@ G6MI_API int g6mi_batch_autotune(int id, int ncl, const g6mi_cluster *cl, int ni
   g6mi_batch_tuning win = base;
   double win_ms = INFINITY;
   const int max_wg = batch_waves(h->prec);
-  for (int iw : {1, 2, 4, 8, 16})
-    for (int wm : {257, 512, 1024})
+  for (int iw : {1, 2, 4, 8, 16, 32, 64})
+    for (int wm : {257, 512, 1024, 1 << 30})
       for (int wg = 1; wg <= max_wg && rc == 0; ++wg) {
         g6mi_batch_tuning t = base;
         t.item_work = iw;

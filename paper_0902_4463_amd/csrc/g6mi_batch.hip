@@ -66,9 +66,11 @@ __device__ __forceinline__ int first_above(const int *inc, int q) {
 // ntiles j-tiles in nsplit splits of `per` tiles, nib * nsplit items.  One
 // tile costs a lane ipw pairs (narrow blocks) or 512 (wide blocks).  Items
 // cost about the same: per = target / ipw tiles, where the target is
-// item_work * 512 lane-pairs, lowered (down to one tile) until the whole
+// item_work * 128 lane-pairs, lowered (down to one tile) until the whole
 // batch makes at least about one item per persistent workgroup, so that a
-// batch of few or small clusters still spreads over the GPU.
+// batch of few or small clusters still spreads over the GPU.  A narrow
+// block holds at most the target's worth of i-particles (not below
+// kBatchMinIpw), so that one tile of it stays within the target.
 //
 // Pass 1 checks the descriptors, picks the block shape of each cluster
 // (kept in its plan entry) and adds up the batch's work; pass 1b cuts the
@@ -122,7 +124,8 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
       ipw = 2 * kWG;
       l2 = 9;
     } else {
-      while (ipw < ni && ipw < kWG) {
+      const long long cap = max(static_cast<long long>(kBatchMinIpw), static_cast<long long>(b.tune.item_work) * 128);
+      while (ipw < ni && ipw < kWG && 2 * ipw <= cap) {
         ipw <<= 1;
         ++l2;
       }
@@ -176,7 +179,7 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
     work += work_all;
   }
   const long long spread = work / max(1, b.grid);
-  const long long target = max(1LL, min(static_cast<long long>(b.tune.item_work) * (2 * kWG), spread));
+  const long long target = max(1LL, min(static_cast<long long>(b.tune.item_work) * 128, spread));
 
   // pass 2: splits, the scans (each thread reads back its own pass-1 entries)
   // and the item -> cluster and i-block -> cluster tables, filled by all

@@ -156,11 +156,11 @@ hipError_t launch_force_spatial(bool nbl, const ForceArgs &a, const SpatialBufs 
 constexpr int kBatchMinIpw = G6MI_BATCH_MIN_IPW;
 
 // Launch policy of a batch (see BatchPlan): item_work = work per item in
-// units of one tile x 512 i-particles, wide_min = smallest cluster block
+// units of 128 lane-pairs (a quarter of one tile x 512 i-particles), wide_min = smallest cluster block
 // that uses two i-particles per lane, max_split = cap on j-splits per
 // cluster (bounds the partial-sum buffer).
 struct BatchTune {
-  int item_work = 2;
+  int item_work = 8;
   int wide_min = 512;
   int max_split = 64;
 };

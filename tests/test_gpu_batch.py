@@ -449,7 +449,7 @@ def test_batch_autotune_and_cache(g6, sess, tmp_path):
     assert rc == g6.OK, g6.last_error(sess.id)
     assert g6.g6mi_batch_get_tuning(sess.id) == best
     lines = path.read_text().splitlines()
-    assert len(lines) == 1 and lines[0].startswith("g6mi-batch-tune-v1 ")
+    assert len(lines) == 1 and lines[0].startswith("g6mi-batch-tune-v2 ")
     _say(f"[autotune] {lines[0]}")
     g6.check(sess.id, b.run(sess.id))
     check_rows(g6, sess.id, b.fetch(), ref, cb, xp, xi, "autotuned", lists=False)
@@ -467,7 +467,7 @@ def test_batch_autotune_and_cache(g6, sess, tmp_path):
     parts[-1] = f"lj{int(np.floor(np.log2(float(np.sum(cl2['nj'])))))}"
     key = "/".join(parts)
     with open(path, "a") as f:
-        f.write(f"g6mi-batch-tune-v1 {key} 3 300 1 7 0.5\n")
+        f.write(f"g6mi-batch-tune-v2 {key} 3 300 1 7 0.5\n")
     rc, got = g6.g6mi_batch_autotune(sess.id, cl2, n2, *b.args(), cache_path=str(path))
     assert rc == g6.OK
     assert got == dict(item_work=3, wide_min=300, wg_per_cu=1, max_split=7), (got, key)
