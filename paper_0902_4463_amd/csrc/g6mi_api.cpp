@@ -1617,14 +1617,13 @@ G6MI_API int g6mi_hermite_init(int id, int n, double eps2, double h2, double eta
   c.desc = g6mi_cluster{0, n, 0, 0, t0, eps2};
   std::memcpy(hs.h_ctl.p, &c, sizeof(c));
   HIPCHK(h, hipMemcpyAsync(a.ctl, hs.h_ctl.p, sizeof(c), hipMemcpyHostToDevice, s));
-  HIPCHK(h, launch_hs_reset(a, s));
-  HIPCHK(h, launch_hs_select(a, s));
   BatchArgs b;
   rc = hs_batch(*h, b);
   if (rc) return rc;
-  HIPCHK(h, launch_batch_plan(b, s));
+  HIPCHK(h, launch_hs_reset(a, s));
+  HIPCHK(h, launch_hs_select(a, b, s));
   HIPCHK(h, launch_batch_force(h->prec, b, batch_grid(*h, h->prec), s));
-  HIPCHK(h, launch_hs_correct(a, true, s));
+  HIPCHK(h, launch_hs_start(a, s));
   rc = hs_read_ctl(*h, s, c);
   if (rc) return rc;
   h->c_have = false; // the work buffers now hold the integrator's block
@@ -1658,10 +1657,9 @@ G6MI_API int g6mi_hermite_advance(int id, double t_end, long long max_steps, dou
   if (!hs.exec || key != hs.key) {
     hs_destroy_graph(*h);
     HIPCHK(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    hipError_t e = launch_hs_select(a, s);
-    if (e == hipSuccess) e = launch_batch_plan(b, s);
-    if (e == hipSuccess) e = launch_batch_force(h->prec, b, grid, s);
-    if (e == hipSuccess) e = launch_hs_correct(a, false, s);
+    hipError_t e = launch_hs_select(a, b, s);
+    if (e == hipSuccess) e = launch_batch_items(h->prec, b, grid, s);
+    if (e == hipSuccess) e = launch_hs_correct(a, b, grid, s);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(s, &g);
     if (e == hipSuccess) e = ec;

@@ -21,7 +21,7 @@
 // fills the 256 compute units when every single cluster is far too small to
 // do so, and removes the per-call launches.
 
-#include "g6mi_device.h"
+#include "g6mi_batch_common.h"
 
 namespace g6mi {
 
@@ -119,38 +119,16 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
       ni = nj = 0;
     }
     if (c < b.ncl && !ok) atomicOr(&s_flags, kFlagBadCluster);
-    int ipw = 1, l2 = 0;
-    if (ni >= b.tune.wide_min) {
-      ipw = 2 * kWG;
-      l2 = 9;
-    } else {
-      const long long cap = max(static_cast<long long>(kBatchMinIpw), static_cast<long long>(b.tune.item_work) * 128);
-      while (ipw < ni && ipw < kWG && 2 * ipw <= cap) {
-        ipw <<= 1;
-        ++l2;
-      }
-    }
-    const int nib = ni > 0 ? (ni + ipw - 1) / ipw : 0;
-    const int ntiles = (nj + kTile - 1) / kTile;
-    if (c < b.ncl) {
-      BatchPlan pl{}; // shape now, splits in pass 2
-      pl.ipw = ipw;
-      pl.log2ipw = l2;
-      pl.nib = nib;
-      pl.per = ntiles;
-      pl.ni = ni;
-      b.plan[c] = pl;
-    }
+    const BatchPlan pl = plan_shape(ni, nj, b.tune); // splits in pass 2
+    if (c < b.ncl) b.plan[c] = pl;
     long long work_all;
-    wg_scan<long long>(static_cast<long long>(nib) * ntiles * ipw, s_part, work_all);
+    wg_scan<long long>(plan_work(pl), s_part, work_all);
     work += work_all;
     c_rows += rows_all;
   }
-  // pass 1b: a cluster whose i-blocks cannot make its share of the
-  // persistent workgroups even with the most splits (one tile each, at most
-  // max_split) takes smaller i-blocks, down to kBatchMinIpw, with more lanes
-  // per i-particle: a lone block of 340 against 32768 particles then runs as
-  // 11 blocks of 32 in 704 items instead of 2 blocks of 256 in 128 items
+  // pass 1b: clusters too small for their share of the persistent
+  // workgroups (plan_share); the share is the grid times the cluster's
+  // fraction of the batch's work
   const long long work0 = max(1LL, work);
   work = 0;
   for (int c0 = 0; c0 < b.ncl; c0 += 256) {
@@ -159,27 +137,16 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
     if (c < b.ncl) {
       BatchPlan pl = b.plan[c];
       if (pl.nib > 0) {
-        const int ni = pl.ni;
-        const int ntiles = pl.per;
-        const long long share = (static_cast<long long>(b.grid) * pl.nib * ntiles * pl.ipw + work0 - 1) / work0;
-        const int most = min(max(ntiles, 1), b.tune.max_split);
-        if (static_cast<long long>(pl.nib) * most < share) {
-          while (pl.ipw > kBatchMinIpw && static_cast<long long>(pl.nib) * most < share) {
-            pl.ipw = min(pl.ipw >> 1, kWG);
-            pl.log2ipw = __builtin_ctz(pl.ipw);
-            pl.nib = (ni + pl.ipw - 1) / pl.ipw;
-          }
-          b.plan[c] = pl;
-        }
-        w = static_cast<long long>(pl.nib) * ntiles * pl.ipw;
+        const long long share = (static_cast<long long>(b.grid) * plan_work(pl) + work0 - 1) / work0;
+        if (plan_share(pl, share, b.tune)) b.plan[c] = pl;
+        w = plan_work(pl);
       }
     }
     long long work_all;
     wg_scan<long long>(w, s_part, work_all);
     work += work_all;
   }
-  const long long spread = work / max(1, b.grid);
-  const long long target = max(1LL, min(static_cast<long long>(b.tune.item_work) * 128, spread));
+  const long long target = plan_target(work, b.grid, b.tune);
 
   // pass 2: splits, the scans (each thread reads back its own pass-1 entries)
   // and the item -> cluster and i-block -> cluster tables, filled by all
@@ -189,19 +156,14 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
   long long c_pent = 0;
   for (int c0 = 0; c0 < b.ncl; c0 += 256) {
     const int c = c0 + tid;
-    int nsplit = 1, per = 1, nib = 0, ni = 0;
+    int nsplit = 1, nib = 0, ni = 0;
     BatchPlan pl{};
     if (c < b.ncl) {
       pl = b.plan[c];
+      plan_splits(pl, target, b.tune);
       nib = pl.nib;
       ni = pl.ni;
-      const int ntiles = pl.per;
-      per = static_cast<int>(max(1LL, min(static_cast<long long>(max(ntiles, 1)), target / pl.ipw)));
-      nsplit = ntiles > 0 ? (ntiles + per - 1) / per : 1;
-      if (nsplit > b.tune.max_split) {
-        per = (ntiles + b.tune.max_split - 1) / b.tune.max_split;
-        nsplit = (ntiles + per - 1) / per;
-      }
+      nsplit = pl.nsplit;
     }
     const long long pent = static_cast<long long>(ni) * nsplit;
     long long items_all, nib_all, pent_all;
@@ -209,8 +171,6 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
     const int nibs = static_cast<int>(wg_scan<long long>(nib, s_part, nib_all));
     const long long pents = wg_scan<long long>(pent, s_part, pent_all);
     if (c < b.ncl) {
-      pl.nsplit = nsplit;
-      pl.per = per;
       pl.ib0 = c_nib + nibs - nib;
       pl.item0 = c_items + items - nib * nsplit;
       pl.pbase = c_pent + pents - pent;
@@ -334,34 +294,10 @@ __global__ __launch_bounds__(kWG, wide_waves<PREC>()) void batch_kernel(BatchArg
 // fence per item would write back the XCD's whole L2 (buffer_wbl2) and an
 // acquire invalidate it, once per item.
 __global__ __launch_bounds__(kWG) void batch_reduce_kernel(BatchArgs b) {
-  const int tid = threadIdx.x;
   const int nib_total = b.work->nib;
-  for (int ibg = blockIdx.x; ibg < nib_total; ibg += gridDim.x) {
-    const int c = __builtin_amdgcn_readfirstlane(b.ib_cl[ibg]);
-    const g6mi_cluster d = b.cl[c];
-    const BatchPlan p = b.plan[c];
-    const int ib = ibg - p.ib0;
-    const int ipw = p.ipw;
-    const int G = min(split_lanes(p.nsplit, 1), max(1, kWG / ipw));
-    int ioff, g, xs;
-    split_lane_map(tid & 63, G, ioff, g, xs);
-    int fl = 0;
-    for (int k0 = 0; k0 < ipw; k0 += kWG / G) {
-      const int k = k0 + (tid >> 6) * xs + ioff;
-      const int il = ib * ipw + k;
-      if (k < ipw && il < d.ni) {
-        const size_t e = static_cast<size_t>(p.pbase) + il;
-        double sum[7], best;
-        int bslot;
-        split_sum(p.nsplit, G, g, xs, b.part + e, static_cast<size_t>(d.ni), b.pcap, b.nn_r2 + e, b.nn_slot + e,
-                  static_cast<size_t>(d.ni), sum, best, bslot);
-        if (g == 0)
-          fl |= finish_out(sum, best, bslot, d.ioff + il, b.jm.index, b.fa.nb_count, b.fa.nb_slot, b.nbl != 0,
-                           b.acc, b.jerk, b.pot, b.nnb, b.r2nn, b.status, b.ovf_list, b.ovf_tag, c);
-      }
-    }
-    if (fl) atomicOr(b.status + kStatusFlags, fl);
-  }
+  int fl = 0;
+  for (int ibg = blockIdx.x; ibg < nib_total; ibg += gridDim.x) fl |= reduce_iblock(b, ibg, [](int) {});
+  if (fl) atomicOr(b.status + kStatusFlags, fl);
 }
 
 // ------------------------------------------------- neighbour-list overflow
@@ -407,13 +343,20 @@ static void launch_batch_prec(const BatchArgs &b, int grid, hipStream_t s) {
     hipLaunchKernelGGL((batch_kernel<PREC, false>), dim3(grid), dim3(kWG), 0, s, b);
 }
 
-hipError_t launch_batch_force(int prec, const BatchArgs &b, int grid, hipStream_t s) {
+hipError_t launch_batch_items(int prec, const BatchArgs &b, int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   switch (prec) {
   case G6MI_PREC_FP32: launch_batch_prec<G6MI_PREC_FP32>(b, grid, s); break;
   case G6MI_PREC_DS: launch_batch_prec<G6MI_PREC_DS>(b, grid, s); break;
   default: launch_batch_prec<G6MI_PREC_FP64>(b, grid, s);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_force(int prec, const BatchArgs &b, int grid, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  const hipError_t e = launch_batch_items(prec, b, grid, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(batch_reduce_kernel, dim3(grid), dim3(kWG), 0, s, b);
   return hipGetLastError();
 }

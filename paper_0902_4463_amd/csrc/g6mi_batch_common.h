@@ -1,0 +1,115 @@
+// Device pieces of the batched launch shared by the batch kernels
+// (g6mi_batch.hip) and the device-resident block steps (g6mi_hermite.hip):
+// the per-cluster launch plan and the reduction of one i-block's split
+// partials.
+
+#pragma once
+
+#include "g6mi_device.h"
+
+namespace g6mi {
+
+// Block shape of a cluster of ni i-particles against nj j-slots: two
+// i-particles per lane from wide_min on, else the next power of two up to
+// 256 and up to the item target (item_work * 128 lane-pairs, not below
+// kBatchMinIpw), so that one tile of a narrow block stays within the target.
+// The tile count is kept in per until the splits are chosen.
+__device__ __forceinline__ BatchPlan plan_shape(int ni, int nj, const BatchTune &t) {
+  BatchPlan pl{};
+  int ipw = 1, l2 = 0;
+  if (ni >= t.wide_min) {
+    ipw = 2 * kWG;
+    l2 = 9;
+  } else {
+    const long long cap = max(static_cast<long long>(kBatchMinIpw), static_cast<long long>(t.item_work) * 128);
+    while (ipw < ni && ipw < kWG && 2 * ipw <= cap) {
+      ipw <<= 1;
+      ++l2;
+    }
+  }
+  pl.ipw = ipw;
+  pl.log2ipw = l2;
+  pl.nib = ni > 0 ? (ni + ipw - 1) / ipw : 0;
+  pl.per = (nj + kTile - 1) / kTile;
+  pl.ni = ni;
+  return pl;
+}
+
+// Lane-pairs of a shaped cluster (one tile costs a lane ipw pairs on a
+// narrow block, 512 on a wide one).
+__device__ __forceinline__ long long plan_work(const BatchPlan &pl) {
+  return static_cast<long long>(pl.nib) * pl.per * pl.ipw;
+}
+
+// A cluster whose i-blocks cannot make `share` items even with the most
+// splits (one tile each, at most max_split) takes smaller i-blocks, down to
+// kBatchMinIpw, with more lanes per i-particle: a lone block of 340 against
+// 32768 particles then runs as 11 blocks of 32 in 704 items instead of 2
+// blocks of 256 in 128 items.  Returns whether the shape changed.
+__device__ __forceinline__ bool plan_share(BatchPlan &pl, long long share, const BatchTune &t) {
+  const int most = min(max(pl.per, 1), t.max_split);
+  if (pl.nib == 0 || static_cast<long long>(pl.nib) * most >= share) return false;
+  while (pl.ipw > kBatchMinIpw && static_cast<long long>(pl.nib) * most < share) {
+    pl.ipw = min(pl.ipw >> 1, kWG);
+    pl.log2ipw = __builtin_ctz(pl.ipw);
+    pl.nib = (pl.ni + pl.ipw - 1) / pl.ipw;
+  }
+  return true;
+}
+
+// Item target in lane-pairs: item_work * 128, lowered (down to one) until
+// the batch's work makes about one item per persistent workgroup.
+__device__ __forceinline__ long long plan_target(long long work, int grid, const BatchTune &t) {
+  return max(1LL, min(static_cast<long long>(t.item_work) * 128, work / max(1, grid)));
+}
+
+// Tiles per split and split count of a shaped cluster for the item target,
+// at most max_split splits.
+__device__ __forceinline__ void plan_splits(BatchPlan &pl, long long target, const BatchTune &t) {
+  const int ntiles = pl.per;
+  int per = static_cast<int>(max(1LL, min(static_cast<long long>(max(ntiles, 1)), target / pl.ipw)));
+  int nsplit = ntiles > 0 ? (ntiles + per - 1) / per : 1;
+  if (nsplit > t.max_split) {
+    per = (ntiles + t.max_split - 1) / t.max_split;
+    nsplit = (ntiles + per - 1) / per;
+  }
+  pl.per = per;
+  pl.nsplit = nsplit;
+}
+
+// The float64 sum of i-block ibg's split partials (split_sum, G lanes per
+// i-particle as the splits and the workgroup allow, laid out by
+// split_lane_map) and its rows' results (finish_out).  Every thread of the
+// workgroup calls it with the same ibg; epi(row) runs on the lane that wrote
+// row `row`, after the write.  Returns the status flags of this thread's rows.
+template <class Epi> __device__ __forceinline__ int reduce_iblock(const BatchArgs &b, int ibg, Epi &&epi) {
+  const int tid = threadIdx.x;
+  const int c = __builtin_amdgcn_readfirstlane(b.ib_cl[ibg]);
+  const g6mi_cluster d = b.cl[c];
+  const BatchPlan p = b.plan[c];
+  const int ib = ibg - p.ib0;
+  const int ipw = p.ipw;
+  const int G = min(split_lanes(p.nsplit, 1), max(1, kWG / ipw));
+  int ioff, g, xs;
+  split_lane_map(tid & 63, G, ioff, g, xs);
+  int fl = 0;
+  for (int k0 = 0; k0 < ipw; k0 += kWG / G) {
+    const int k = k0 + (tid >> 6) * xs + ioff;
+    const int il = ib * ipw + k;
+    if (k < ipw && il < d.ni) {
+      const size_t e = static_cast<size_t>(p.pbase) + il;
+      double sum[7], best;
+      int bslot;
+      split_sum(p.nsplit, G, g, xs, b.part + e, static_cast<size_t>(d.ni), b.pcap, b.nn_r2 + e, b.nn_slot + e,
+                static_cast<size_t>(d.ni), sum, best, bslot);
+      if (g == 0) {
+        fl |= finish_out(sum, best, bslot, d.ioff + il, b.jm.index, b.fa.nb_count, b.fa.nb_slot, b.nbl != 0, b.acc,
+                         b.jerk, b.pot, b.nnb, b.r2nn, b.status, b.ovf_list, b.ovf_tag, c);
+        epi(d.ioff + il);
+      }
+    }
+  }
+  return fl;
+}
+
+} // namespace g6mi

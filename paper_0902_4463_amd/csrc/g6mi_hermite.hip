@@ -7,11 +7,11 @@
 //                      a and jerk); t_b = min_k (t_k + dt_k) was gathered by
 //                      the previous step: the others' times here, the
 //                      corrected ones' in hs_correct_kernel
-//   hs_publish_kernel  the one-cluster descriptor that the batched force
-//                      launch reads
-//   batch_plan_kernel, batch_kernel, batch_reduce_kernel
-//                      forces on the block (g6mi_batch.hip)
-//   hs_correct_kernel  Hermite corrector, Aarseth time step, power-of-two
+//   hs_publish_kernel  the one-cluster descriptor and launch plan that the
+//                      batched force kernel reads
+//   batch_kernel       forces on the block (g6mi_batch.hip)
+//   hs_correct_kernel  the split partials added (the batch reduction), then
+//                      the Hermite corrector, Aarseth time step, power-of-two
 //                      block quantisation; the corrected particle is written
 //                      back into the j-memory (its a/2 and jerk/6 too)
 //
@@ -20,7 +20,7 @@
 // The integrator's formulas follow the host driver (hermite/driver.py) term
 // by term, with float contraction switched off so that both round alike.
 
-#include "g6mi_device.h"
+#include "g6mi_batch_common.h"
 
 namespace g6mi {
 
@@ -106,31 +106,56 @@ __global__ __launch_bounds__(256) void hs_select_kernel(HermiteArgs h) {
 }
 
 // The block as a one-cluster descriptor for the batched force launch, or an
-// empty block once t_b > t_end, so that replays past the end change nothing;
-// then the block-time keys turn over (see HermiteCtl).
-// A launch of its own after the selection: a last-workgroup hand-over inside
-// it would need a device-scope fence per workgroup, which on gfx950 writes
-// back and invalidates the XCD's whole L2.
-__global__ __launch_bounds__(64) void hs_publish_kernel(HermiteArgs h) {
-  if (threadIdx.x != 0) return;
-  HermiteCtl *ctl = h.ctl;
-  const int ph = ctl->phase;
-  const double tb = key_value(ctl->key[ph]);
-  const bool go = tb <= ctl->t_end;
-  g6mi_cluster d;
-  d.joff = 0;
-  d.nj = h.n;
-  d.ioff = 0;
-  d.ni = go ? ctl->ni_count : 0;
-  d.ti = go ? tb : ctl->time;
-  d.eps2 = h.eps2;
-  ctl->desc = d;
-  ctl->done = go ? 0 : 1;
-  // the corrector adds the block's new times to key[ph ^ 1]; the next
-  // selection reads it and fills key[ph] afresh
-  ctl->ni_count = 0;
-  ctl->key[ph] = kKeyInf;
-  ctl->phase = ph ^ 1;
+// empty block once t_b > t_end, so that replays past the end change nothing,
+// with the batch's launch plan for that one cluster (the plan kernel's
+// decisions for a batch of one: plan_shape, plan_share with the whole grid
+// as its share, plan_target, plan_splits) and its work tables; then the
+// block-time keys turn over (see HermiteCtl).  A launch of its own after the
+// selection: a last-workgroup hand-over inside the selection would need a
+// device-scope fence per workgroup, which on gfx950 writes back and
+// invalidates the XCD's whole L2.
+__global__ __launch_bounds__(256) void hs_publish_kernel(HermiteArgs h, BatchArgs b) {
+  __shared__ int s_items, s_nib, s_ni;
+  if (threadIdx.x == 0) {
+    HermiteCtl *ctl = h.ctl;
+    const int ph = ctl->phase;
+    const double tb = key_value(ctl->key[ph]);
+    const bool go = tb <= ctl->t_end;
+    g6mi_cluster d;
+    d.joff = 0;
+    d.nj = h.n;
+    d.ioff = 0;
+    d.ni = go ? ctl->ni_count : 0;
+    d.ti = go ? tb : ctl->time;
+    d.eps2 = h.eps2;
+    ctl->desc = d;
+    ctl->done = go ? 0 : 1;
+    BatchPlan pl = plan_shape(d.ni, d.nj, b.tune);
+    if (pl.nib > 0) plan_share(pl, b.grid, b.tune);
+    plan_splits(pl, plan_target(plan_work(pl), b.grid, b.tune), b.tune);
+    pl.ib0 = pl.item0 = 0;
+    pl.pbase = 0;
+    b.plan[0] = pl;
+    const int items = pl.nib * pl.nsplit;
+    b.work->head = 0;
+    b.work->nitems = min(items, b.item_cap);
+    b.work->nib = pl.nib;
+    b.status[kStatusFlags] = items > b.item_cap ? kFlagBadCluster : 0;
+    b.status[kStatusOverflowCount] = 0;
+    s_items = min(items, b.item_cap);
+    s_nib = pl.nib;
+    s_ni = d.ni;
+    // the corrector adds the block's new times to key[ph ^ 1]; the next
+    // selection reads it and fills key[ph] afresh
+    ctl->ni_count = 0;
+    ctl->key[ph] = kKeyInf;
+    ctl->phase = ph ^ 1;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < s_items; q += 256) b.item_cl[q] = 0;
+  for (int q = threadIdx.x; q < s_nib; q += 256) b.ib_cl[q] = 0;
+  if (b.nbl)
+    for (int r = threadIdx.x; r < s_ni; r += 256) b.fa.nb_count[r] = 0;
 }
 
 __device__ __forceinline__ double norm3(const double *a) {
@@ -206,21 +231,28 @@ __device__ __forceinline__ double correct_particle(const HermiteArgs &h, int q, 
   return nw;
 }
 
-// The block's particles corrected (correct_particle, one thread each) and
-// the minimum of their new t + dt folded into the next block time.
-__global__ __launch_bounds__(256) void hs_correct_kernel(HermiteArgs h) {
+// The block's forces finished from the split partials (reduce_iblock, one
+// workgroup per i-block, grid-strided) and each particle corrected by the
+// lane that finished it (correct_particle); the minimum of their new t + dt
+// is folded into the next block time.
+__global__ __launch_bounds__(256) void hs_correct_kernel(HermiteArgs h, BatchArgs b) {
   HermiteCtl *ctl = h.ctl;
   const int ni = ctl->desc.ni;
   const double tb = ctl->desc.ti;
-  const int q = blockIdx.x * 256 + threadIdx.x;
   if (blockIdx.x == 0 && threadIdx.x == 0 && ni > 0) {
     ctl->block_steps += 1;
     ctl->particle_steps += ni;
     ctl->time = tb;
   }
-  if (blockIdx.x * 256 >= ni) return; // whole workgroups past the block
   unsigned long long next = kKeyInf;
-  if (q < ni) next = order_key(tb + correct_particle(h, q, tb));
+  int fl = 0;
+  const int nib_total = b.work->nib;
+  for (int ibg = blockIdx.x; ibg < nib_total; ibg += gridDim.x)
+    fl |= reduce_iblock(b, ibg, [&](int q) {
+      const unsigned long long key = order_key(tb + correct_particle(h, q, tb));
+      next = key < next ? key : next;
+    });
+  if (fl) atomicOr(b.status + kStatusFlags, fl);
   // the next block time, second part: this block's particles
   key_min(next, &ctl->key[ctl->phase]);
 }
@@ -292,16 +324,17 @@ hipError_t launch_hs_reset(const HermiteArgs &h, hipStream_t s) {
   hipLaunchKernelGGL(hs_reset_kernel, grid_n(h.n), dim3(256), 0, s, h);
   return hipGetLastError();
 }
-hipError_t launch_hs_select(const HermiteArgs &h, hipStream_t s) {
+hipError_t launch_hs_select(const HermiteArgs &h, const BatchArgs &b, hipStream_t s) {
   hipLaunchKernelGGL(hs_select_kernel, grid_n(h.n), dim3(256), 0, s, h);
-  hipLaunchKernelGGL(hs_publish_kernel, dim3(1), dim3(64), 0, s, h);
+  hipLaunchKernelGGL(hs_publish_kernel, dim3(1), dim3(256), 0, s, h, b);
   return hipGetLastError();
 }
-hipError_t launch_hs_correct(const HermiteArgs &h, bool start, hipStream_t s) {
-  if (start)
-    hipLaunchKernelGGL(hs_start_kernel, grid_n(h.n), dim3(256), 0, s, h);
-  else
-    hipLaunchKernelGGL(hs_correct_kernel, grid_n(h.n), dim3(256), 0, s, h);
+hipError_t launch_hs_start(const HermiteArgs &h, hipStream_t s) {
+  hipLaunchKernelGGL(hs_start_kernel, grid_n(h.n), dim3(256), 0, s, h);
+  return hipGetLastError();
+}
+hipError_t launch_hs_correct(const HermiteArgs &h, const BatchArgs &b, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(hs_correct_kernel, dim3(static_cast<unsigned>(grid > 0 ? grid : 1)), dim3(256), 0, s, h, b);
   return hipGetLastError();
 }
 

@@ -205,7 +205,10 @@ struct BatchArgs {
 constexpr int kPlanZeroChunk = 4096;
 
 hipError_t launch_batch_plan(const BatchArgs &b, hipStream_t s);
+// the persistent kernel and the reduction
 hipError_t launch_batch_force(int prec, const BatchArgs &b, int grid, hipStream_t s);
+// the persistent kernel alone (its partials reduced by the caller's launch)
+hipError_t launch_batch_items(int prec, const BatchArgs &b, int grid, hipStream_t s);
 hipError_t launch_batch_nb_exact(int prec, const BatchArgs &b, int novf, hipStream_t s);
 
 // Status flag of the batched launch: a cluster descriptor was out of range
@@ -249,9 +252,14 @@ struct HermiteArgs {
 };
 
 hipError_t launch_hs_reset(const HermiteArgs &h, hipStream_t s);
-// next block time and the block itself (two launches)
-hipError_t launch_hs_select(const HermiteArgs &h, hipStream_t s);
-// corrector and new steps (start = the first evaluation: store and pick steps)
-hipError_t launch_hs_correct(const HermiteArgs &h, bool start, hipStream_t s);
+// the block due at the next block time, its descriptor and its one-cluster
+// batch plan in b (two launches)
+hipError_t launch_hs_select(const HermiteArgs &h, const BatchArgs &b, hipStream_t s);
+// after the first force evaluation (a whole batched force launch): store a,
+// jerk and potential and pick the first steps
+hipError_t launch_hs_start(const HermiteArgs &h, hipStream_t s);
+// after launch_batch_items: the batch reduction, corrector and new steps in
+// one launch of `grid` workgroups
+hipError_t launch_hs_correct(const HermiteArgs &h, const BatchArgs &b, int grid, hipStream_t s);
 
 } // namespace g6mi
