@@ -212,10 +212,13 @@ __device__ __forceinline__ void store_partial(const BatchArgs &b, size_t e, cons
   b.nn_slot[e] = bslot;
 }
 
-// Persistent workgroups: take the next item until the queue is empty (every
-// wave reaches the exit: items are finite and each workgroup takes one item
-// per round).  Partial entry of i-particle il (cluster row) in split s:
-// pbase + s * ni + il, component-major over pcap entries.
+// Persistent workgroups: workgroup g starts with item g, then takes the
+// next item from the queue (grid + one atomic counter) until the items run
+// out (every wave reaches the exit: items are finite and each workgroup
+// takes one item per round).  The first round needs no atomic: hundreds of
+// workgroups incrementing one counter at once queue up behind each other.
+// Partial entry of i-particle il (cluster row) in split s: pbase + s * ni +
+// il, component-major over pcap entries.
 template <int PREC, bool NBL>
 __global__ __launch_bounds__(kWG, wide_waves<PREC>()) void batch_kernel(BatchArgs b) {
   using R = real_t<PREC>;
@@ -226,14 +229,9 @@ __global__ __launch_bounds__(kWG, wide_waves<PREC>()) void batch_kernel(BatchArg
   const int tid = threadIdx.x;
   const int nitems = b.work->nitems;
 
-  for (;;) {
-    __syncthreads(); // the previous item is done with the LDS and s_item
-    if (tid == 0) s_item = atomicAdd(&b.work->head, 1);
-    __syncthreads();
-    // uniform across the workgroup: the item's cluster, descriptor and plan
-    // are then scalar loads held in scalar registers
-    const int q = __builtin_amdgcn_readfirstlane(s_item);
-    if (q >= nitems) break;
+  for (int q = blockIdx.x; q < nitems;) {
+    // q is uniform across the workgroup: the item's cluster, descriptor and
+    // plan are then scalar loads held in scalar registers
     const int c = b.item_cl[q];
     const g6mi_cluster d = b.cl[c];
     const BatchPlan p = b.plan[c];
@@ -282,7 +280,11 @@ __global__ __launch_bounds__(kWG, wide_waves<PREC>()) void batch_kernel(BatchArg
       n.lane_sum(reinterpret_cast<double *>(lds), tid, lil, ipw, bestd, bslot);
       if (n.sub == 0 && n.valid) store_partial(b, e0 + il, n.t, bestd, bslot);
     }
-
+    if (static_cast<int>(gridDim.x) >= nitems) break; // no second round
+    __syncthreads(); // the item is done with the LDS and s_item
+    if (tid == 0) s_item = static_cast<int>(gridDim.x) + atomicAdd(&b.work->head, 1);
+    __syncthreads();
+    q = __builtin_amdgcn_readfirstlane(s_item);
   }
 }
 
