@@ -298,7 +298,7 @@ __global__ __launch_bounds__(kWG, wide_waves<PREC>()) void batch_kernel(BatchArg
 __global__ __launch_bounds__(kWG) void batch_reduce_kernel(BatchArgs b) {
   const int nib_total = b.work->nib;
   int fl = 0;
-  for (int ibg = blockIdx.x; ibg < nib_total; ibg += gridDim.x) fl |= reduce_iblock(b, ibg, [](int) {});
+  for (int ibg = blockIdx.x; ibg < nib_total; ibg += gridDim.x) fl |= reduce_iblock(b, ibg, [](int, const double *) {});
   if (fl) atomicOr(b.status + kStatusFlags, fl);
 }
 

@@ -80,8 +80,9 @@ __device__ __forceinline__ void plan_splits(BatchPlan &pl, long long target, con
 // The float64 sum of i-block ibg's split partials (split_sum, G lanes per
 // i-particle as the splits and the workgroup allow, laid out by
 // split_lane_map) and its rows' results (finish_out).  Every thread of the
-// workgroup calls it with the same ibg; epi(row) runs on the lane that wrote
-// row `row`, after the write.  Returns the status flags of this thread's rows.
+// workgroup calls it with the same ibg; epi(row, sum) runs on the lane that
+// wrote row `row`, after the write, with the row's sums (acc xyz, jerk xyz,
+// sum m/r).  Returns the status flags of this thread's rows.
 template <class Epi> __device__ __forceinline__ int reduce_iblock(const BatchArgs &b, int ibg, Epi &&epi) {
   const int tid = threadIdx.x;
   const int c = __builtin_amdgcn_readfirstlane(b.ib_cl[ibg]);
@@ -105,7 +106,7 @@ template <class Epi> __device__ __forceinline__ int reduce_iblock(const BatchArg
       if (g == 0) {
         fl |= finish_out(sum, best, bslot, d.ioff + il, b.jm.index, b.fa.nb_count, b.fa.nb_slot, b.nbl != 0, b.acc,
                          b.jerk, b.pot, b.nnb, b.r2nn, b.status, b.ovf_list, b.ovf_tag, c);
-        epi(d.ioff + il);
+        epi(d.ioff + il, static_cast<const double *>(sum));
       }
     }
   }

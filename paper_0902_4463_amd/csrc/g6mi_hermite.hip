@@ -173,10 +173,12 @@ __device__ __forceinline__ double quantise(double dt, double dt_min, double dt_m
 }
 
 // Corrector (Makino & Aarseth 1992) for block position q at block time tb,
-// then the Aarseth criterion with the second derivative at the end of the
-// step, and the block rule: halve while too long, double only when the time
-// is a multiple of the doubled step.  Returns the new step.
-__device__ __forceinline__ double correct_particle(const HermiteArgs &h, int q, double tb) {
+// given its new force sums f (acc xyz, jerk xyz, sum m/r, as the batch
+// reduction wrote them to acc1, jrk1 and pot1 = -f[6]), then the Aarseth
+// criterion with the second derivative at the end of the step, and the
+// block rule: halve while too long, double only when the time is a multiple
+// of the doubled step.  Returns the new step.
+__device__ __forceinline__ double correct_particle(const HermiteArgs &h, int q, double tb, const double *f) {
 #pragma clang fp contract(off)
   HermiteCtl *ctl = h.ctl;
   const int k = h.active[q];
@@ -187,8 +189,8 @@ __device__ __forceinline__ double correct_particle(const HermiteArgs &h, int q, 
   for (int d = 0; d < 3; ++d) {
     a0[d] = h.acc[d * cap + k];
     j0[d] = h.jrk[d * cap + k];
-    a1[d] = h.acc1[3 * static_cast<size_t>(q) + d];
-    j1[d] = h.jrk1[3 * static_cast<size_t>(q) + d];
+    a1[d] = f[d];
+    j1[d] = f[3 + d];
     finite = finite && isfinite(a1[d]) && isfinite(j1[d]);
   }
   const double dt2 = dt * dt, dt3 = dt2 * dt, dt4 = dt3 * dt, dt5 = dt4 * dt;
@@ -226,7 +228,7 @@ __device__ __forceinline__ double correct_particle(const HermiteArgs &h, int q, 
   if (dt_new >= 2.0 * old && fmod(tb, 2.0 * old) == 0.0 && 2.0 * old <= h.dt_max) nw = 2.0 * old;
   h.jm.t[k] = tb;
   h.dt[k] = nw;
-  h.pot[k] = h.pot1[q];
+  h.pot[k] = -f[6];
   if (!finite) atomicOr(&ctl->flags, 1);
   return nw;
 }
@@ -248,8 +250,8 @@ __global__ __launch_bounds__(256) void hs_correct_kernel(HermiteArgs h, BatchArg
   int fl = 0;
   const int nib_total = b.work->nib;
   for (int ibg = blockIdx.x; ibg < nib_total; ibg += gridDim.x)
-    fl |= reduce_iblock(b, ibg, [&](int q) {
-      const unsigned long long key = order_key(tb + correct_particle(h, q, tb));
+    fl |= reduce_iblock(b, ibg, [&](int q, const double *sum) {
+      const unsigned long long key = order_key(tb + correct_particle(h, q, tb, sum));
       next = key < next ? key : next;
     });
   if (fl) atomicOr(b.status + kStatusFlags, fl);
