@@ -37,7 +37,9 @@ __device__ __forceinline__ double key_value(unsigned long long k) {
 constexpr unsigned long long kKeyInf = 0xfff0000000000000ull; // order_key(+inf)
 
 // Workgroup minimum of one key per thread, folded into *dst with one
-// atomic (none when every key is +inf).  Every thread must call it.
+// atomic (none when every key is +inf).  Every thread must call it, at most
+// once per launch (its LDS words are read after the barrier without a second
+// one).
 __device__ __forceinline__ void key_min(unsigned long long key, unsigned long long *dst) {
   __shared__ unsigned long long s_key[4];
   for (int off = 32; off > 0; off >>= 1) {
