@@ -12,7 +12,12 @@ Prints one JSON line: pair interactions/s (value) and Gflop/s at 60 flop per
 interaction (the paper's convention, Sec. 3.1), the interaction kernel's
 fraction of the vector-ALU roofline measured with HIP events on the launch
 stream, the float64 variant's throughput, error statistics of a sample
-against the CPU oracle, and the oracle's own rate on the host cores.
+against the CPU oracle, the oracle's own rate on the host cores, and the
+batched workload (256 independent clusters in one launch).
+
+Diagnostic modes: --sweep k,... adds blocks of 2^k active particles;
+--batched-only runs only the batched workload (its record is the JSON
+line), with --batched-tuning fixing its launch policy instead of autotuning.
 """
 
 from __future__ import annotations

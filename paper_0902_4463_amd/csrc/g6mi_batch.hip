@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
     c_pent += pent_all;
   }
   if (tid == 0) {
-    b.work->head = 0;
+    for (int x = 0; x < kQueues; ++x) b.work->head[x] = 0;
     b.work->nitems = min(c_items, b.item_cap);
     b.work->nib = c_nib;
     // more items than the table holds cannot happen with the host's bound;
@@ -213,10 +213,14 @@ __device__ __forceinline__ void store_partial(const BatchArgs &b, size_t e, cons
 }
 
 // Persistent workgroups: workgroup g starts with item g, then takes the
-// next item from the queue (grid + one atomic counter) until the items run
-// out (every wave reaches the exit: items are finite and each workgroup
-// takes one item per round).  The first round needs no atomic: hundreds of
-// workgroups incrementing one counter at once queue up behind each other.
+// next item from its queue until the items run out (every wave reaches the
+// exit: items are finite and each workgroup takes one item per round).  The
+// items after the first grid's worth are dealt round-robin to kQueues
+// queues, one counter each, and workgroup g takes from queue g mod kQueues:
+// workgroups go to the 8 XCDs round-robin, so each XCD's workgroups share
+// one counter, and no counter serves the whole grid.  The first round needs
+// no atomic at all: hundreds of workgroups incrementing one counter at once
+// queue up behind each other.
 // Partial entry of i-particle il (cluster row) in split s: pbase + s * ni +
 // il, component-major over pcap entries.
 template <int PREC, bool NBL>
@@ -282,7 +286,12 @@ __global__ __launch_bounds__(kWG, wide_waves<PREC>()) void batch_kernel(BatchArg
     }
     if (static_cast<int>(gridDim.x) >= nitems) break; // no second round
     __syncthreads(); // the item is done with the LDS and s_item
-    if (tid == 0) s_item = static_cast<int>(gridDim.x) + atomicAdd(&b.work->head, 1);
+    if (tid == 0) {
+      // every queue needs a workgroup: one queue for a grid smaller than kQueues
+      const int nq = static_cast<int>(gridDim.x) >= kQueues ? kQueues : 1;
+      const int x = static_cast<int>(blockIdx.x) % nq;
+      s_item = static_cast<int>(gridDim.x) + x + nq * atomicAdd(&b.work->head[x], 1);
+    }
     __syncthreads();
     q = __builtin_amdgcn_readfirstlane(s_item);
   }

@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void hs_publish_kernel(HermiteArgs h, BatchArg
     pl.pbase = 0;
     b.plan[0] = pl;
     const int items = pl.nib * pl.nsplit;
-    b.work->head = 0;
+    for (int x = 0; x < kQueues; ++x) b.work->head[x] = 0;
     b.work->nitems = min(items, b.item_cap);
     b.work->nib = pl.nib;
     b.status[kStatusFlags] = items > b.item_cap ? kFlagBadCluster : 0;

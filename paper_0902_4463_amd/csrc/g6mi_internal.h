@@ -176,9 +176,12 @@ struct BatchPlan {
   long long pbase;
 };
 
-// Work-queue state: next item, number of items (written by the plan kernel).
+// Work-queue state (written by the plan kernel): one counter per XCD group
+// of workgroups (see batch_kernel), the number of items and of i-blocks.
+constexpr int kQueues = 8;
 struct BatchWork {
-  int head, nitems, nib, pad;
+  int head[kQueues];
+  int nitems, nib;
 };
 
 struct BatchArgs {
