@@ -5,6 +5,7 @@ the oracle's predictor and sums with the oracle's force routine)."""
 import numpy as np
 
 import oracle
+from tests import parity
 
 
 class OracleBackend:
@@ -35,3 +36,42 @@ class OracleBackend:
 
     def close(self):
         pass
+
+
+class Shadowed:
+    """GPU backend plus an oracle copy of the same j-memory; each force call
+    is compared with the oracle (all i, or a seeded sample of ``cap``)."""
+
+    def __init__(self, n, eps2, precision, cap=None, handle=2):
+        from hermite import G6Backend
+        self.gpu = G6Backend(n, eps2, precision=precision, handle=handle)
+        self.ref = OracleBackend(n, eps2)
+        self.cap = cap
+        self.worst = dict(acc=0.0, jerk=0.0, pot=0.0)
+        self.fails = []
+        self.checked = 0
+        self.rng = np.random.default_rng(0)
+        self.record = []  # per force call: (ti, ni, checked, acc_max, jerk_max, pot_max, conditioned)
+
+    def set_j(self, st, sel):
+        self.gpu.set_j(st, sel)
+        self.ref.set_j(st, sel)
+
+    def force(self, ti, index, xi, vi):
+        acc, jerk, pot = self.gpu.force(ti, index, xi, vi)
+        pick = np.arange(len(index))
+        if self.cap is not None and len(index) > self.cap:
+            pick = np.sort(self.rng.choice(len(index), self.cap, replace=False))
+        r = self.ref.force(ti, index[pick], xi[pick], vi[pick], conditioning=True)
+        rep = parity.force_report(dict(acc=acc[pick], jerk=jerk[pick], pot=pot[pick]), r)
+        self.checked += len(pick)
+        for k, key in (("acc", "acc_max"), ("jerk", "jerk_max"), ("pot", "pot_max")):
+            self.worst[k] = max(self.worst[k], rep[key])
+        if not rep["ok"]:
+            self.fails.append((ti, len(index), rep))
+        self.record.append((float(ti), len(index), len(pick), rep["acc_max"], rep["jerk_max"], rep["pot_max"],
+                            rep["acc_conditioned"] + rep["jerk_conditioned"]))
+        return acc, jerk, pot
+
+    def close(self):
+        self.gpu.close()

@@ -8,9 +8,8 @@ import numpy as np
 import pytest
 
 import workloads
-from hermite import BlockStepIntegrator, G6Backend, HermiteState
-from tests import parity
-from tests.hermite_oracle import OracleBackend
+from hermite import BlockStepIntegrator, HermiteState
+from tests.hermite_oracle import OracleBackend, Shadowed
 
 pytestmark = pytest.mark.gpu
 
@@ -18,41 +17,6 @@ pytestmark = pytest.mark.gpu
 def _say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
-
-
-class Shadowed:
-    """GPU backend plus an oracle copy of the same j-memory; each force call
-    is compared with the oracle (all i, or a seeded sample of ``cap``)."""
-
-    def __init__(self, n, eps2, precision, cap=None):
-        self.gpu = G6Backend(n, eps2, precision=precision, handle=2)
-        self.ref = OracleBackend(n, eps2)
-        self.cap = cap
-        self.worst = dict(acc=0.0, jerk=0.0, pot=0.0)
-        self.fails = []
-        self.checked = 0
-        self.rng = np.random.default_rng(0)
-
-    def set_j(self, st, sel):
-        self.gpu.set_j(st, sel)
-        self.ref.set_j(st, sel)
-
-    def force(self, ti, index, xi, vi):
-        acc, jerk, pot = self.gpu.force(ti, index, xi, vi)
-        pick = np.arange(len(index))
-        if self.cap is not None and len(index) > self.cap:
-            pick = np.sort(self.rng.choice(len(index), self.cap, replace=False))
-        r = self.ref.force(ti, index[pick], xi[pick], vi[pick], conditioning=True)
-        rep = parity.force_report(dict(acc=acc[pick], jerk=jerk[pick], pot=pot[pick]), r)
-        self.checked += len(pick)
-        for k, key in (("acc", "acc_max"), ("jerk", "jerk_max"), ("pot", "pot_max")):
-            self.worst[k] = max(self.worst[k], rep[key])
-        if not rep["ok"]:
-            self.fails.append((ti, len(index), rep))
-        return acc, jerk, pot
-
-    def close(self):
-        self.gpu.close()
 
 
 def energy_drift(st, it, t_end):
