@@ -318,15 +318,32 @@ __device__ __forceinline__ void fold(Sums<R> &ts, Totals &t) {
   ts.zero();
 }
 
+// Group sums g into the float32 tile sums ts, or straight into the float64
+// totals t when `close` (the group holds a new nearest neighbour).  A close
+// neighbour's terms can exceed the whole force several times over where the
+// rest cancels them; in a float32 tile sum every later group would then
+// round against that large partial (a particle of conditioning 10 in a long
+// run lost 2e-6 of its acceleration so).  New nearest neighbours come rarely
+// after the first few groups, so the float64 path is seldom taken.  Used by
+// the narrow blocks (one i-particle per lane, registers to spare); in the
+// two-per-lane kernels the branch's registers spill.
+template <class R>
+__device__ __forceinline__ void fold_or_add(Sums<R> &g, Sums<R> &ts, Totals &t, bool close) {
+  if (close) fold(g, t);
+  else ts.add(g);
+}
+
 // Per-pair path for tiles holding an own slot or the ragged end: the pair
 // terms go through group sums of kGroup pairs (float32 variants) before the
 // tile sums, as on the grouped path.  FOLD: each full group goes straight
-// into the float64 totals instead (see WideLanes::tile).
-template <int PREC, bool NBL, bool FOLD = false>
+// into the float64 totals instead (see WideLanes::tile); RECORD: a group that
+// brought a new nearest neighbour does (fold_or_add).
+template <int PREC, bool NBL, bool FOLD = false, bool RECORD = false>
 struct MaskedRun {
   using R = real_t<PREC>;
   Sums<R> g;
   int n = 0;
+  R best0 = R(INFINITY); // RECORD: the nearest-neighbour distance when the group began
   __device__ __forceinline__ void start() {
     g.zero();
     n = 0;
@@ -337,9 +354,12 @@ struct MaskedRun {
     if constexpr (PREC == G6MI_PREC_FP64) {
       pair<PREC, true, NBL>(st, ts, rec, jslot, islot, eps2, h2, best, bslot, nb_count, nb_row);
     } else {
+      if constexpr (RECORD)
+        if (n == 0) best0 = best;
       pair<PREC, true, NBL>(st, g, rec, jslot, islot, eps2, h2, best, bslot, nb_count, nb_row);
       if (++n == kGroup) {
         if constexpr (FOLD) fold(g, tot);
+        else if constexpr (RECORD) fold_or_add(g, ts, tot, best < best0);
         else ts.add(g);
         start();
       }
@@ -633,7 +653,7 @@ struct NarrowLane {
     if (cnt < kTile || K < kGroup || __any(self_here)) {
       int *nb_cnt = nb_count + (valid ? row : 0);
       int *nb_row = nb_slot + static_cast<size_t>(valid ? row : 0) * kNbMax;
-      MaskedRun<PREC, NBL> run;
+      MaskedRun<PREC, NBL, false, true> run;
       run.start();
       for (int jj = sub; jj < cnt; jj += L)
         run.step(st, ts, t, tl + jj * REC, jbase + jj, slot, eps2, h2, ebest, eslot, nb_cnt, nb_row);
@@ -652,7 +672,7 @@ struct NarrowLane {
 #pragma unroll
           for (int u = 1; u < kGroup; ++u)
             m = fmin(m, pair_core<PREC>(st, gs, tl + (sub + ((k0 + u) << log2L)) * REC, eps2));
-          ts.add(gs);
+          fold_or_add(gs, ts, t, m < gbest);
         }
         if (m < gbest) {
           gbest = m;

@@ -30,11 +30,13 @@ def main(argv=None):
     ap.add_argument("--precision", choices=["ds", "fp32", "fp64"], default="ds")
     ap.add_argument("--cap", type=int, default=1024)
     ap.add_argument("--t-end", type=float, default=1.0)
+    ap.add_argument("--dump", default=None, help="npz file for the inputs of the first failing calls")
     args = ap.parse_args(argv)
     jm = workloads.config_c2()
     eps2 = jm.meta["eps2"]
     st = HermiteState(jm.x, jm.v, jm.m)
     b = Shadowed(jm.n, eps2, args.precision, cap=args.cap)
+    b.keep_fail_inputs = args.dump is not None
     w0 = time.perf_counter()
     try:
         it = BlockStepIntegrator(st, b, eta=0.01, dt_max=2.0 ** -4)
@@ -50,6 +52,9 @@ def main(argv=None):
             k += 1
     finally:
         b.close()
+    if args.dump and b.fail_inputs:
+        np.savez_compressed(args.dump, eps2=eps2, **{f"{k}_{q}": v for q, d in enumerate(b.fail_inputs)
+                                                     for k, v in d.items()})
     rec = np.array([r[1:] for r in b.record], dtype=float)
     ni, checked, acc, jerk, pot, cond = rec.T
     out = dict(config="c2", n=jm.n, precision=args.precision, eta=0.01, t_end=args.t_end, cap=args.cap,

@@ -52,6 +52,8 @@ class Shadowed:
         self.checked = 0
         self.rng = np.random.default_rng(0)
         self.record = []  # per force call: (ti, ni, checked, acc_max, jerk_max, pot_max, conditioned)
+        self.keep_fail_inputs = False  # keep the inputs and results of the first failing calls
+        self.fail_inputs = []
 
     def set_j(self, st, sel):
         self.gpu.set_j(st, sel)
@@ -69,6 +71,12 @@ class Shadowed:
             self.worst[k] = max(self.worst[k], rep[key])
         if not rep["ok"]:
             self.fails.append((ti, len(index), rep))
+            if self.keep_fail_inputs and len(self.fail_inputs) < 4:
+                xp, vp = self.ref.jmemory(ti)
+                self.fail_inputs.append(dict(ti=ti, index=np.asarray(index)[pick], xi=xi[pick], vi=vi[pick],
+                                             acc=acc[pick], jerk=jerk[pick], pot=pot[pick], ref_acc=r["acc"],
+                                             ref_jerk=r["jerk"], ref_pot=r["pot"], xj=xp, vj=vp, mj=self.ref.m.copy(),
+                                             jindex=self.ref.index.copy()))
         self.record.append((float(ti), len(index), len(pick), rep["acc_max"], rep["jerk_max"], rep["pot_max"],
                             rep["acc_conditioned"] + rep["jerk_conditioned"]))
         return acc, jerk, pot
