@@ -464,9 +464,13 @@ struct WideLanes {
 
   // The cnt records at positions jbase .. jbase + cnt - 1 staged at tl.
   // FOLD: the float32 group sums go straight into the float64 totals, with
-  // no float32 tile level; used where a tile gathers a particle's close
-  // neighbours (spatial order), whose large terms of both signs would
-  // otherwise cancel in one float32 tile sum.
+  // no float32 tile level.  Large terms of both signs from close neighbours
+  // would otherwise cancel in one float32 tile sum, and every later group
+  // would round against them.  The spatial kernel folds its near tiles; the
+  // unordered DS kernels fold every tile (a particle of conditioning 9.5 in
+  // a long run lost 2.1e-6 of its acceleration in the tile sum; folding cost
+  // about 2.5% there).  Unlike fold_or_add it needs no branch, whose
+  // registers spill heavily in these two-per-lane kernels.
   template <bool FOLD = false>
   __device__ __forceinline__ void tile(const float4 *__restrict__ tl, int jbase, int cnt, R eps2,
                                        int *__restrict__ nb_count, int *__restrict__ nb_slot) {
