@@ -298,17 +298,20 @@ __global__ __launch_bounds__(kWG, wide_waves<PREC>()) void batch_kernel(BatchArg
   }
 }
 
-// One workgroup per i-block (grid-strided over the work->nib i-blocks of the
-// batch, ib_cl giving each one's cluster): the float64 sum of the i-block's
-// split partials (split_sum, G lanes per i-particle as the splits and the
-// workgroup allow) and the rows' results (finish_out).  A launch of its own:
-// the kernel boundary makes every item's partials visible, where a release
-// fence per item would write back the XCD's whole L2 (buffer_wbl2) and an
-// acquire invalidate it, once per item.
+// One workgroup per part of an i-block (reduce_parts; grid-strided over the
+// work->nib i-blocks of the batch when they outnumber the grid, ib_cl giving
+// each one's cluster): the float64 sum of the rows' split partials
+// (split_sum, G lanes per i-particle as the splits and the workgroup allow)
+// and their results (finish_out).  A launch of its own: the kernel boundary
+// makes every item's partials visible, where a release fence per item would
+// write back the XCD's whole L2 (buffer_wbl2) and an acquire invalidate it,
+// once per item.
 __global__ __launch_bounds__(kWG) void batch_reduce_kernel(BatchArgs b) {
   const int nib_total = b.work->nib;
+  const int P = reduce_parts(nib_total, static_cast<int>(gridDim.x), 64);
   int fl = 0;
-  for (int ibg = blockIdx.x; ibg < nib_total; ibg += gridDim.x) fl |= reduce_iblock(b, ibg, [](int, const double *) {});
+  for (int u = blockIdx.x; u < nib_total * P; u += gridDim.x)
+    fl |= reduce_iblock(b, u / P, u % P, P, [](int, const double *) {});
   if (fl) atomicOr(b.status + kStatusFlags, fl);
 }
 
@@ -369,7 +372,7 @@ hipError_t launch_batch_force(int prec, const BatchArgs &b, int grid, hipStream_
   if (grid <= 0) return hipSuccess;
   const hipError_t e = launch_batch_items(prec, b, grid, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(batch_reduce_kernel, dim3(grid), dim3(kWG), 0, s, b);
+  hipLaunchKernelGGL(batch_reduce_kernel, dim3(reduce_grid(grid)), dim3(kWG), 0, s, b);
   return hipGetLastError();
 }
 

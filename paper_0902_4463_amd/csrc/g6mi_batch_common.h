@@ -77,27 +77,44 @@ __device__ __forceinline__ void plan_splits(BatchPlan &pl, long long target, con
   pl.nsplit = nsplit;
 }
 
-// The float64 sum of i-block ibg's split partials (split_sum, G lanes per
-// i-particle as the splits and the workgroup allow, laid out by
-// split_lane_map) and its rows' results (finish_out).  Every thread of the
-// workgroup calls it with the same ibg; epi(row, sum) runs on the lane that
-// wrote row `row`, after the write, with the row's sums (acc xyz, jerk xyz,
-// sum m/r).  Returns the status flags of this thread's rows.
-template <class Epi> __device__ __forceinline__ int reduce_iblock(const BatchArgs &b, int ibg, Epi &&epi) {
+// Parts per i-block of a batch reduction over nib i-blocks on a grid of
+// `grid` workgroups: the largest power of two up to `cap` (and 64) that
+// still gives every (i-block, part) a workgroup of its own, else 1 (the
+// grid strides over whole i-blocks).  A part is a contiguous run of the
+// i-block's rows; more parts put more workgroups, and so more loads in
+// flight, on the split partials, whose long sums are bound by latency.
+__device__ __forceinline__ int reduce_parts(int nib, int grid, int cap) {
+  int P = 1;
+  while (2 * P <= min(cap, 64) && static_cast<long long>(nib) * (2 * P) <= grid) P <<= 1;
+  return P;
+}
+
+// The float64 sum of the split partials (split_sum, G lanes per i-particle
+// as the splits and the workgroup allow, laid out by split_lane_map) of part
+// `part` of `nparts` of i-block ibg, and its rows' results (finish_out).
+// The part holds ipw / P consecutive rows, P = min(nparts, ipw) (both powers
+// of two); parts from P on are empty.  Every thread of the workgroup calls
+// it with the same arguments; epi(row, sum) runs on the lane that wrote row
+// `row`, after the write, with the row's sums (acc xyz, jerk xyz, sum m/r).
+// Returns the status flags of this thread's rows.
+template <class Epi>
+__device__ __forceinline__ int reduce_iblock(const BatchArgs &b, int ibg, int part, int nparts, Epi &&epi) {
   const int tid = threadIdx.x;
   const int c = __builtin_amdgcn_readfirstlane(b.ib_cl[ibg]);
   const g6mi_cluster d = b.cl[c];
   const BatchPlan p = b.plan[c];
   const int ib = ibg - p.ib0;
-  const int ipw = p.ipw;
-  const int G = min(split_lanes(p.nsplit, 1), max(1, kWG / ipw));
+  const int P = min(nparts, p.ipw);
+  if (part >= P) return 0;
+  const int rows = p.ipw / P;
+  const int G = min(split_lanes(p.nsplit, 1), max(1, kWG / rows));
   int ioff, g, xs;
   split_lane_map(tid & 63, G, ioff, g, xs);
   int fl = 0;
-  for (int k0 = 0; k0 < ipw; k0 += kWG / G) {
-    const int k = k0 + (tid >> 6) * xs + ioff;
-    const int il = ib * ipw + k;
-    if (k < ipw && il < d.ni) {
+  for (int k0 = 0; k0 < rows; k0 += kWG / G) {
+    const int kk = k0 + (tid >> 6) * xs + ioff;
+    const int il = ib * p.ipw + part * rows + kk;
+    if (kk < rows && il < d.ni) {
       const size_t e = static_cast<size_t>(p.pbase) + il;
       double sum[7], best;
       int bslot;

@@ -236,9 +236,10 @@ __device__ __forceinline__ double correct_particle(const HermiteArgs &h, int q, 
 }
 
 // The block's forces finished from the split partials (reduce_iblock, one
-// workgroup per i-block, grid-strided) and each particle corrected by the
-// lane that finished it (correct_particle); the minimum of their new t + dt
-// is folded into the next block time.
+// workgroup per part of an i-block, at most kHsReduceWgs workgroups with
+// rows) and each particle corrected by the lane that finished it
+// (correct_particle); the minimum of their new t + dt is folded into the
+// next block time, one atomic per workgroup with rows.
 __global__ __launch_bounds__(256) void hs_correct_kernel(HermiteArgs h, BatchArgs b) {
   HermiteCtl *ctl = h.ctl;
   const int ni = ctl->desc.ni;
@@ -251,8 +252,9 @@ __global__ __launch_bounds__(256) void hs_correct_kernel(HermiteArgs h, BatchArg
   unsigned long long next = kKeyInf;
   int fl = 0;
   const int nib_total = b.work->nib;
-  for (int ibg = blockIdx.x; ibg < nib_total; ibg += gridDim.x)
-    fl |= reduce_iblock(b, ibg, [&](int q, const double *sum) {
+  const int P = reduce_parts(nib_total, min(static_cast<int>(gridDim.x), kHsReduceWgs), 64);
+  for (int u = blockIdx.x; u < nib_total * P; u += gridDim.x)
+    fl |= reduce_iblock(b, u / P, u % P, P, [&](int q, const double *sum) {
       const unsigned long long key = order_key(tb + correct_particle(h, q, tb, sum));
       next = key < next ? key : next;
     });
@@ -338,7 +340,7 @@ hipError_t launch_hs_start(const HermiteArgs &h, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t launch_hs_correct(const HermiteArgs &h, const BatchArgs &b, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(hs_correct_kernel, dim3(static_cast<unsigned>(grid > 0 ? grid : 1)), dim3(256), 0, s, h, b);
+  hipLaunchKernelGGL(hs_correct_kernel, dim3(static_cast<unsigned>(reduce_grid(grid > 0 ? grid : 1))), dim3(256), 0, s, h, b);
   return hipGetLastError();
 }
 

@@ -176,6 +176,23 @@ struct BatchPlan {
   long long pbase;
 };
 
+// Workgroups of a batch reduction (batch_reduce_kernel, hs_correct_kernel)
+// for a persistent grid of `grid`: kReduceGridMul times as many, so that
+// the i-blocks of a small batch are cut into parts (reduce_parts) and
+// their split sums run with more loads in flight.
+#ifndef G6MI_REDUCE_GRID_MUL
+#define G6MI_REDUCE_GRID_MUL 4
+#endif
+constexpr int kReduceGridMul = G6MI_REDUCE_GRID_MUL;
+__host__ __device__ constexpr int reduce_grid(int grid) { return grid * kReduceGridMul; }
+
+// Most workgroups with rows in hs_correct_kernel: each ends with one atomic
+// on the next block time, and a burst of them on one address queues up.
+#ifndef G6MI_HS_REDUCE_WGS
+#define G6MI_HS_REDUCE_WGS 256
+#endif
+constexpr int kHsReduceWgs = G6MI_HS_REDUCE_WGS;
+
 // Work-queue state (written by the plan kernel): one counter per XCD group
 // of workgroups (see batch_kernel), the number of items and of i-blocks.
 constexpr int kQueues = 8;
