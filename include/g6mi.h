@@ -364,9 +364,12 @@ int g6mi_batch_use_graph(int id, int on);
  *              block below wide_min is also cut into i-blocks of at most
  *              item_work * 128 particles
  *   wide_min   clusters with at least this many i-particles use two
- *              i-particles per lane (default 512)
+ *              i-particles per lane (default 512); above ni_total, a batch
+ *              runs a kernel without the two-per-lane path, whose
+ *              registers allow four workgroups per compute unit
  *   wg_per_cu  persistent workgroups per compute unit (0: the kernel's
- *              occupancy, 3, or 2 for float64; 1 .. 8)
+ *              occupancy, 3, or 2 for float64, or 4 without the
+ *              two-per-lane path; 1 .. 8)
  *   max_split  most j-splits per cluster (1 .. 4096; default 64; lowered
  *              so that the partial sums stay within 4 GiB) */
 typedef struct g6mi_batch_tuning {

@@ -605,10 +605,17 @@ constexpr size_t kBatchPartialBudget = size_t(4) << 30;
 constexpr size_t kPartialEntryBytes = 7 * sizeof(double) + sizeof(double) + sizeof(int);
 constexpr int kBatchMaxClusters = 1 << 20;
 
-int batch_waves(int prec) { return prec == G6MI_PREC_FP64 ? 2 : 3; }
+// Persistent workgroups per CU that the batch kernel's registers allow: the
+// narrow-only kernel (no cluster of the batch can take wide blocks) fits four.
+int batch_waves(int prec, bool narrow) { return narrow ? kNarrowWaves : prec == G6MI_PREC_FP64 ? 2 : 3; }
 
-int batch_grid(const Handle &h, int prec) {
-  const int w = h.b_wg_per_cu > 0 ? h.b_wg_per_cu : batch_waves(prec);
+// Whether a batch over ni_total rows runs the narrow-only kernel: a cluster
+// takes wide blocks from wide_min i-particles on, and none has more than
+// ni_total.
+bool batch_narrow(const Handle &h, int ni_total) { return h.btune.wide_min > ni_total; }
+
+int batch_grid(const Handle &h, int prec, bool narrow) {
+  const int w = h.b_wg_per_cu > 0 ? h.b_wg_per_cu : batch_waves(prec, narrow);
   return std::max(1, h.ncu) * w;
 }
 
@@ -707,7 +714,8 @@ int prepare_batch(Handle &h, int ncl, const g6mi_cluster *d_cl, int ni_total, in
   b.nj_set = nj_set;
   b.ni_total = ni_total;
   b.item_cap = static_cast<int>(item_cap);
-  b.grid = batch_grid(h, h.prec);
+  b.wide = batch_narrow(h, ni_total) ? 0 : 1;
+  b.grid = batch_grid(h, h.prec, b.wide == 0);
   b.tune = tune;
   b.jm = h.jm;
   b.fa.xi = d_xi;
@@ -747,7 +755,7 @@ int enqueue_batch(Handle &h, int ncl, const g6mi_cluster *d_cl, int ni_total, co
                      d_jerk, d_pot, d_nnb, d_r2nn, b);
   if (rc) return rc;
   const BatchTune &tune = b.tune;
-  const int grid = batch_grid(h, h.prec);
+  const int grid = b.grid;
 
   h.shape[0] = 0;
   h.shape[1] = tune.max_split;
@@ -1463,10 +1471,9 @@ G6MI_API int g6mi_batch_autotune(int id, int ncl, const g6mi_cluster *cl, int ni
   const g6mi_batch_tuning base = current_tuning(*h);
   g6mi_batch_tuning win = base;
   double win_ms = INFINITY;
-  const int max_wg = batch_waves(h->prec);
   for (int iw : {1, 2, 4, 8, 16, 32, 64})
     for (int wm : {257, 512, 1024, 1 << 30})
-      for (int wg = 1; wg <= max_wg && rc == 0; ++wg) {
+      for (int wg = 1; wg <= batch_waves(h->prec, wm > ni_total) && rc == 0; ++wg) {
         g6mi_batch_tuning t = base;
         t.item_work = iw;
         t.wide_min = wm;
@@ -1622,7 +1629,7 @@ G6MI_API int g6mi_hermite_init(int id, int n, double eps2, double h2, double eta
   if (rc) return rc;
   HIPCHK(h, launch_hs_reset(a, s));
   HIPCHK(h, launch_hs_select(a, b, s));
-  HIPCHK(h, launch_batch_force(h->prec, b, batch_grid(*h, h->prec), s));
+  HIPCHK(h, launch_batch_force(h->prec, b, b.grid, s));
   HIPCHK(h, launch_hs_start(a, s));
   rc = hs_read_ctl(*h, s, c);
   if (rc) return rc;
@@ -1652,7 +1659,7 @@ G6MI_API int g6mi_hermite_advance(int id, double t_end, long long max_steps, dou
   BatchArgs b;
   rc = hs_batch(*h, b);
   if (rc) return rc;
-  const int grid = batch_grid(*h, h->prec);
+  const int grid = b.grid;
   std::vector<uint64_t> key = graph_key(*h, b, grid, s);
   if (!hs.exec || key != hs.key) {
     hs_destroy_graph(*h);

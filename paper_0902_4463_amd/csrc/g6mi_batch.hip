@@ -223,8 +223,11 @@ __device__ __forceinline__ void store_partial(const BatchArgs &b, size_t e, cons
 // queue up behind each other.
 // Partial entry of i-particle il (cluster row) in split s: pbase + s * ni +
 // il, component-major over pcap entries.
-template <int PREC, bool NBL>
-__global__ __launch_bounds__(kWG, wide_waves<PREC>()) void batch_kernel(BatchArgs b) {
+// WIDE = false: the narrow-only kernel, for batches whose plan cannot make a
+// wide block (the host launches it only when tune.wide_min > ni_total); its
+// registers fit four waves per SIMD.
+template <int PREC, bool NBL, bool WIDE>
+__global__ __launch_bounds__(kWG, WIDE ? wide_waves<PREC>() : kNarrowWaves) void batch_kernel(BatchArgs b) {
   using R = real_t<PREC>;
   constexpr int REC = rec4<PREC>();
   __shared__ __attribute__((aligned(16))) unsigned char lds[narrow_lds_bytes<PREC>()];
@@ -249,7 +252,10 @@ __global__ __launch_bounds__(kWG, wide_waves<PREC>()) void batch_kernel(BatchArg
     const R eps2 = static_cast<R>(d.eps2);
     const size_t e0 = static_cast<size_t>(p.pbase) + static_cast<size_t>(sp) * d.ni;
 
-    if (p.ipw == 2 * kWG) {
+    if (!WIDE && p.ipw > kWG) {
+      // not reached (see above); the item is dropped and the batch flagged
+      if (tid == 0) atomicOr(b.status + kStatusFlags, kFlagBadCluster);
+    } else if (WIDE && p.ipw == 2 * kWG) {
       const int il0 = ib * (2 * kWG) + tid, il1 = il0 + kWG;
       WideLanes<PREC, NBL> w;
       w.init(b.fa, d.ioff + il0, d.ioff + il1, il0 < d.ni, il1 < d.ni);
@@ -352,10 +358,17 @@ hipError_t launch_batch_plan(const BatchArgs &b, hipStream_t s) {
 
 template <int PREC>
 static void launch_batch_prec(const BatchArgs &b, int grid, hipStream_t s) {
-  if (b.nbl)
-    hipLaunchKernelGGL((batch_kernel<PREC, true>), dim3(grid), dim3(kWG), 0, s, b);
-  else
-    hipLaunchKernelGGL((batch_kernel<PREC, false>), dim3(grid), dim3(kWG), 0, s, b);
+  if (b.wide) {
+    if (b.nbl)
+      hipLaunchKernelGGL((batch_kernel<PREC, true, true>), dim3(grid), dim3(kWG), 0, s, b);
+    else
+      hipLaunchKernelGGL((batch_kernel<PREC, false, true>), dim3(grid), dim3(kWG), 0, s, b);
+  } else {
+    if (b.nbl)
+      hipLaunchKernelGGL((batch_kernel<PREC, true, false>), dim3(grid), dim3(kWG), 0, s, b);
+    else
+      hipLaunchKernelGGL((batch_kernel<PREC, false, false>), dim3(grid), dim3(kWG), 0, s, b);
+  }
 }
 
 hipError_t launch_batch_items(int prec, const BatchArgs &b, int grid, hipStream_t s) {

@@ -155,6 +155,10 @@ hipError_t launch_force_spatial(bool nbl, const ForceArgs &a, const SpatialBufs 
 #endif
 constexpr int kBatchMinIpw = G6MI_BATCH_MIN_IPW;
 
+// Waves per SIMD of the narrow-only batch kernel (one i-particle per lane;
+// its registers fit four).
+constexpr int kNarrowWaves = 4;
+
 // Launch policy of a batch (see BatchPlan): item_work = work per item in
 // units of 128 lane-pairs (a quarter of one tile x 512 i-particles), wide_min = smallest cluster block
 // that uses two i-particles per lane, max_split = cap on j-splits per
@@ -208,6 +212,8 @@ struct BatchArgs {
   BatchWork *work = nullptr;
   int ncl = 0, nj_set = 0, ni_total = 0, item_cap = 0;
   int grid = 1;            // persistent workgroups of batch_kernel
+  int wide = 1;            // 0: no cluster can take wide blocks (tune.wide_min > ni_total), and the
+                           // batch runs the narrow-only kernel, whose registers allow more waves
   BatchTune tune;
   JMem jm;
   ForceArgs fa;            // i-arrays over rows 0..ni_total-1; nb_count, nb_slot

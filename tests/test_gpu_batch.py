@@ -204,13 +204,15 @@ def test_batch_parity(g6, sess, prec):
 TUNINGS = [dict(item_work=1, wide_min=1, wg_per_cu=1, max_split=1),
            dict(item_work=16, wide_min=100000, wg_per_cu=2, max_split=64),
            dict(item_work=2, wide_min=257, wg_per_cu=3, max_split=3),
-           dict(item_work=1, wide_min=512, wg_per_cu=8, max_split=4096)]
+           dict(item_work=1, wide_min=512, wg_per_cu=8, max_split=4096),
+           dict(item_work=4, wide_min=2 ** 30, wg_per_cu=0, max_split=64)]
 
 
 @pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: "iw{item_work}-wm{wide_min}-wg{wg_per_cu}-ms{max_split}".format(**t))
 def test_batch_launch_policies(g6, sess, tuning):
     """Every launch policy (items of one tile to whole clusters, wide or
-    narrow blocks, 1..8 workgroups per compute unit) gives oracle parity."""
+    narrow blocks, 1..8 workgroups per compute unit, the narrow-only kernel
+    when wide_min exceeds the batch's rows) gives oracle parity."""
     cb, xp, vp, xi, vi, h2, ref = small_case()
     sess.load(cb.jm)
     g6.check(sess.id, g6.g6mi_batch_set_tuning(sess.id, tuning))
