@@ -66,6 +66,9 @@ def run_device(args, jm, t_end, dt_max, marks):
     g6.check(hid, g6.g6_open(hid))
     g6.check(hid, g6.g6mi_set_precision(hid, args.precision))
     g6.check(hid, g6.g6mi_set_neighbour_lists(hid, False))
+    if args.batch_tuning:
+        iw, wm, wg, ms = (int(x) for x in args.batch_tuning.split(","))
+        g6.check(hid, g6.g6mi_batch_set_tuning(hid, dict(item_work=iw, wide_min=wm, wg_per_cu=wg, max_split=ms)))
     g6.check(hid, g6.g6mi_set_j_particles(hid, jm.n, np.arange(jm.n), jm.index, np.zeros(jm.n), None, jm.m,
                                           np.zeros((jm.n, 3)), np.zeros((jm.n, 3)), jm.v, jm.x))
     w0 = time.perf_counter()
@@ -96,6 +99,8 @@ def main(argv=None):
     ap.add_argument("--eta", type=float, default=0.01)
     ap.add_argument("--t-end", type=float, default=None)
     ap.add_argument("--device", action="store_true", help="block steps inside the library, on the GPU")
+    ap.add_argument("--batch-tuning", default=None,
+                    help="item_work,wide_min,wg_per_cu,max_split of the force launches of --device runs")
     args = ap.parse_args(argv)
     jm = workloads.config_c1() if args.config == "c1" else workloads.config_c2()
     t_end = args.t_end if args.t_end is not None else (0.125 if args.config == "c1" else 1.0)
