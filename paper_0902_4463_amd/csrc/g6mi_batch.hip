@@ -266,7 +266,7 @@ __global__ __launch_bounds__(kWG, WIDE ? wide_waves<PREC>() : kNarrowWaves) void
         if (tid < cnt) predict_record<PREC>(b.jm, static_cast<size_t>(jbase + tid), d.ti, tile + tid * REC);
         __syncthreads();
         // DS: every group goes straight to the float64 totals (see WideLanes::tile)
-        w.template tile<PREC == G6MI_PREC_DS>(tile, jbase, cnt, eps2, b.fa.nb_count, b.fa.nb_slot);
+        w.template tile<PREC == G6MI_PREC_DS, true>(tile, jbase, cnt, eps2, b.fa.nb_count, b.fa.nb_slot);
         w.resolve(tile, jbase); // while the tile is still in LDS
       }
       if (w.v0) store_partial(b, e0 + il0, w.t0, static_cast<double>(w.ebest0), w.eslot0);

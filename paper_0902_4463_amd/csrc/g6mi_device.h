@@ -233,9 +233,14 @@ __device__ __forceinline__ void pair(const IState<PREC> &st, Sums<real_t<PREC>> 
 // softening) for the neighbour search.  No self test: the caller only uses
 // it on tiles that hold no i-particle's own slot.  FIRST: the group's first
 // pair sets the sums instead of adding to them.
-template <int PREC, bool FIRST = false>
+// SELF: the pair is the i-particle with its own record when `self`; its
+// inverse distance is taken as zero (every term then adds an exact zero,
+// also at eps2 = 0) and its r^2 as +inf, so that it is neither a nearest
+// neighbour nor a neighbour.
+template <int PREC, bool FIRST = false, bool SELF = false>
 __device__ __forceinline__ real_t<PREC> pair_core(const IState<PREC> &st, Sums<real_t<PREC>> &acc,
-                                                  const float4 *__restrict__ rec, real_t<PREC> eps2) {
+                                                  const float4 *__restrict__ rec, real_t<PREC> eps2,
+                                                  bool self = false) {
   using R = real_t<PREC>;
   R d[3], w[3], mj;
   separation<PREC>(st, rec, d, w, mj);
@@ -244,6 +249,7 @@ __device__ __forceinline__ real_t<PREC> pair_core(const IState<PREC> &st, Sums<r
   R rinv;
   if constexpr (PREC == G6MI_PREC_FP64) rinv = rsqrt_f64(s);
   else rinv = __builtin_amdgcn_rsqf(s);
+  if constexpr (SELF) rinv = self ? R(0) : rinv;
   const R rinv2 = rinv * rinv;
   const R mr = mj * rinv;
   const R mr3 = mr * rinv2;
@@ -266,7 +272,8 @@ __device__ __forceinline__ real_t<PREC> pair_core(const IState<PREC> &st, Sums<r
       acc.j2[k] += mr3t * d[k];
     }
   }
-  return r2u;
+  if constexpr (SELF) return self ? R(INFINITY) : r2u;
+  else return r2u;
 }
 
 // i-particle `row` of the i-arrays in a's layout.  An invalid row (a padding
@@ -388,7 +395,7 @@ __device__ __forceinline__ int rec_slot(const float4 *rec) { return __float_as_i
 template <int PREC, bool SORTED = false>
 __device__ __forceinline__ void resolve_group(const IState<PREC> &st, int &grp, int stride,
                                               const float4 *__restrict__ src, int base,
-                                              real_t<PREC> &best, int &bslot) {
+                                              real_t<PREC> &best, int &bslot, int islot = -1) {
   constexpr int REC = rec4<PREC>();
   if (grp < 0) return;
   for (int u = 0; u < kGroup; ++u) {
@@ -396,6 +403,7 @@ __device__ __forceinline__ void resolve_group(const IState<PREC> &st, int &grp, 
     const float4 *rec = src + static_cast<size_t>(js - base) * REC;
     const real_t<PREC> r = r2_of<PREC>(st, rec);
     const int sl = SORTED ? rec_slot(rec) : js;
+    if (sl == islot) continue; // a group of a self tile (grouped path with SELF)
     if (r < best || (r == best && sl < bslot)) {
       best = r;
       bslot = sl;
@@ -416,9 +424,9 @@ __device__ __forceinline__ void resolve_group(const IState<PREC> &st, int &grp, 
 // is recovered by re-examining that one group (resolve), where the first
 // minimum wins as in a sequential scan.  Neighbour lists need no per-pair
 // test: a group holds a neighbour of i exactly when its minimum r^2 is below
-// h_i^2, and only such groups are re-examined.  Tiles that contain an
-// i-particle's own slot, and ragged tiles, take the per-pair path with
-// explicit self exclusion.
+// h_i^2, and only such groups are re-examined.  Ragged tiles take the
+// per-pair path; tiles that contain an i-particle's own slot take it too, or
+// with SELFG the grouped path with the self pair excluded per pair.
 //
 // SORTED: the j-records are in a spatial order (positions are not slots):
 // own-tile detection uses the own record's position (pos0, pos1, set by the
@@ -471,12 +479,19 @@ struct WideLanes {
   // a long run lost 2.1e-6 of its acceleration in the tile sum; folding cost
   // about 2.5% there).  Unlike fold_or_add it needs no branch, whose
   // registers spill heavily in these two-per-lane kernels.
-  template <bool FOLD = false>
+  //
+  // SELFG (unsorted records only): a full tile holding an own slot takes the
+  // grouped path with the self pair excluded per pair (pair_core's SELF)
+  // instead of the per-pair path.  Where the i-particles are a random subset
+  // of the j-particles (block steps, batches of small clusters) nearly every
+  // tile holds some lane's own slot.
+  template <bool FOLD = false, bool SELFG = false>
   __device__ __forceinline__ void tile(const float4 *__restrict__ tl, int jbase, int cnt, R eps2,
                                        int *__restrict__ nb_count, int *__restrict__ nb_slot) {
+    static_assert(!(SELFG && SORTED), "own records are found by slot");
     const bool self_here =
         (pos0 >= jbase && pos0 < jbase + cnt) || (pos1 >= jbase && pos1 < jbase + cnt);
-    if (cnt < kTile || __any(self_here)) {
+    if (cnt < kTile || (!SELFG && __any(self_here))) {
       MaskedRun<PREC, NBL, FOLD> r0, r1;
       r0.start();
       r1.start();
@@ -490,75 +505,89 @@ struct WideLanes {
       }
       r0.finish(ts0);
       r1.finish(ts1);
+    } else if (SELFG && __any(self_here)) {
+      grouped<FOLD, true>(tl, jbase, eps2, nb_count, nb_slot);
     } else {
-      // bit k of nbm0 / nbm1: group k holds a neighbour of i0 / i1
-      unsigned nbm0 = 0u, nbm1 = 0u;
-#pragma unroll G6MI_GROUP_UNROLL
-      for (int g = 0; g < kTile; g += kGroup) {
-        R m0 = R(INFINITY), m1 = R(INFINITY);
-        if constexpr (PREC == G6MI_PREC_FP64) {
-#pragma unroll
-          for (int u = 0; u < kGroup; ++u) {
-            const float4 *rec = tl + (g + u) * REC;
-            m0 = fmin(m0, pair_core<PREC>(s0, ts0, rec, eps2));
-            m1 = fmin(m1, pair_core<PREC>(s1, ts1, rec, eps2));
-          }
-        } else {
-          Sums<R> g0, g1; // group sums, set by the group's first pair
-          m0 = pair_core<PREC, true>(s0, g0, tl + g * REC, eps2);
-          m1 = pair_core<PREC, true>(s1, g1, tl + g * REC, eps2);
-#pragma unroll
-          for (int u = 1; u < kGroup; ++u) {
-            const float4 *rec = tl + (g + u) * REC;
-            m0 = fmin(m0, pair_core<PREC>(s0, g0, rec, eps2));
-            m1 = fmin(m1, pair_core<PREC>(s1, g1, rec, eps2));
-          }
-          if constexpr (FOLD) {
-            fold(g0, t0);
-            fold(g1, t1);
-          } else {
-            ts0.add(g0);
-            ts1.add(g1);
-          }
-        }
-        if (m0 < gbest0) {
-          gbest0 = m0;
-          grp0 = jbase + g;
-        }
-        if (m1 < gbest1) {
-          gbest1 = m1;
-          grp1 = jbase + g;
-        }
-        if constexpr (NBL) {
-          // the group minimum also tells whether any record is a neighbour
-          nbm0 |= (m0 < h20 ? 1u : 0u) << (g / kGroup);
-          nbm1 |= (m1 < h21 ? 1u : 0u) << (g / kGroup);
-        }
-      }
-      if constexpr (NBL) {
-        // rare: append the neighbours of the flagged groups
-        while (nbm0 | nbm1) {
-          const int k = __builtin_ctz(nbm0 | nbm1);
-          const unsigned bit = 1u << k;
-          for (int u = 0; u < kGroup; ++u) {
-            const int jj = k * kGroup + u;
-            const float4 *rec = tl + jj * REC;
-            if ((nbm0 & bit) && r2_of<PREC>(s0, rec) < h20) nb_append(nb_count, nb_slot, row0, jslot_at(tl, jbase, jj));
-            if ((nbm1 & bit) && r2_of<PREC>(s1, rec) < h21) nb_append(nb_count, nb_slot, row1, jslot_at(tl, jbase, jj));
-          }
-          nbm0 &= ~bit;
-          nbm1 &= ~bit;
-        }
-      }
+      grouped<FOLD, false>(tl, jbase, eps2, nb_count, nb_slot);
     }
     fold(ts0, t0);
     fold(ts1, t1);
   }
 
+  // The grouped path of `tile` over a full tile; SELF: the pair of an
+  // i-particle with its own slot adds zeros and is no (nearest) neighbour.
+  template <bool FOLD, bool SELF>
+  __device__ __forceinline__ void grouped(const float4 *__restrict__ tl, int jbase, R eps2,
+                                          int *__restrict__ nb_count, int *__restrict__ nb_slot) {
+    // own slots relative to the tile (outside 0 .. kTile - 1 when elsewhere)
+    const int o0 = slot0 - jbase, o1 = slot1 - jbase;
+    // bit k of nbm0 / nbm1: group k holds a neighbour of i0 / i1
+    unsigned nbm0 = 0u, nbm1 = 0u;
+#pragma unroll G6MI_GROUP_UNROLL
+    for (int g = 0; g < kTile; g += kGroup) {
+      R m0 = R(INFINITY), m1 = R(INFINITY);
+      if constexpr (PREC == G6MI_PREC_FP64) {
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+          const float4 *rec = tl + (g + u) * REC;
+          m0 = fmin(m0, pair_core<PREC, false, SELF>(s0, ts0, rec, eps2, g + u == o0));
+          m1 = fmin(m1, pair_core<PREC, false, SELF>(s1, ts1, rec, eps2, g + u == o1));
+        }
+      } else {
+        Sums<R> g0, g1; // group sums, set by the group's first pair
+        m0 = pair_core<PREC, true, SELF>(s0, g0, tl + g * REC, eps2, g == o0);
+        m1 = pair_core<PREC, true, SELF>(s1, g1, tl + g * REC, eps2, g == o1);
+#pragma unroll
+        for (int u = 1; u < kGroup; ++u) {
+          const float4 *rec = tl + (g + u) * REC;
+          m0 = fmin(m0, pair_core<PREC, false, SELF>(s0, g0, rec, eps2, g + u == o0));
+          m1 = fmin(m1, pair_core<PREC, false, SELF>(s1, g1, rec, eps2, g + u == o1));
+        }
+        if constexpr (FOLD) {
+          fold(g0, t0);
+          fold(g1, t1);
+        } else {
+          ts0.add(g0);
+          ts1.add(g1);
+        }
+      }
+      if (m0 < gbest0) {
+        gbest0 = m0;
+        grp0 = jbase + g;
+      }
+      if (m1 < gbest1) {
+        gbest1 = m1;
+        grp1 = jbase + g;
+      }
+      if constexpr (NBL) {
+        // the group minimum also tells whether any record is a neighbour
+        nbm0 |= (m0 < h20 ? 1u : 0u) << (g / kGroup);
+        nbm1 |= (m1 < h21 ? 1u : 0u) << (g / kGroup);
+      }
+    }
+    if constexpr (NBL) {
+      // rare: append the neighbours of the flagged groups
+      while (nbm0 | nbm1) {
+        const int k = __builtin_ctz(nbm0 | nbm1);
+        const unsigned bit = 1u << k;
+        for (int u = 0; u < kGroup; ++u) {
+          const int jj = k * kGroup + u;
+          const float4 *rec = tl + jj * REC;
+          if ((nbm0 & bit) && (!SELF || jj != o0) && r2_of<PREC>(s0, rec) < h20)
+            nb_append(nb_count, nb_slot, row0, jslot_at(tl, jbase, jj));
+          if ((nbm1 & bit) && (!SELF || jj != o1) && r2_of<PREC>(s1, rec) < h21)
+            nb_append(nb_count, nb_slot, row1, jslot_at(tl, jbase, jj));
+        }
+        nbm0 &= ~bit;
+        nbm1 &= ~bit;
+      }
+    }
+  }
+
   // Resolve the pending groups from records at src (position js at js - base).
   __device__ __forceinline__ void resolve(const float4 *__restrict__ src, int base) {
-    resolve_group<PREC, SORTED>(s0, grp0, 1, src, base, ebest0, eslot0);
-    resolve_group<PREC, SORTED>(s1, grp1, 1, src, base, ebest1, eslot1);
+    resolve_group<PREC, SORTED>(s0, grp0, 1, src, base, ebest0, eslot0, slot0);
+    resolve_group<PREC, SORTED>(s1, grp1, 1, src, base, ebest1, eslot1, slot1);
   }
 
   // A full far tile in float32 records relative to the tile's centre
@@ -651,10 +680,13 @@ struct NarrowLane {
     grp = eslot = -1;
   }
 
+  // A full tile holding an own slot takes the grouped path with the self
+  // pair excluded per pair (pair_core's SELF); ragged tiles and tiles of
+  // fewer than kGroup records per lane take the per-pair path.
   __device__ __forceinline__ void tile(const float4 *__restrict__ tl, int jbase, int cnt, R eps2,
                                        int *__restrict__ nb_count, int *__restrict__ nb_slot) {
     const bool self_here = slot >= jbase && slot < jbase + cnt;
-    if (cnt < kTile || K < kGroup || __any(self_here)) {
+    if (cnt < kTile || K < kGroup) {
       int *nb_cnt = nb_count + (valid ? row : 0);
       int *nb_row = nb_slot + static_cast<size_t>(valid ? row : 0) * kNbMax;
       MaskedRun<PREC, NBL, false, true> run;
@@ -662,44 +694,57 @@ struct NarrowLane {
       for (int jj = sub; jj < cnt; jj += L)
         run.step(st, ts, t, tl + jj * REC, jbase + jj, slot, eps2, h2, ebest, eslot, nb_cnt, nb_row);
       run.finish(ts);
+    } else if (__any(self_here)) {
+      grouped<true>(tl, jbase, eps2, nb_count, nb_slot);
     } else {
-      unsigned nbm = 0u;
-      for (int k0 = 0; k0 < K; k0 += kGroup) {
-        R m = R(INFINITY);
-        if constexpr (PREC == G6MI_PREC_FP64) {
-#pragma unroll
-          for (int u = 0; u < kGroup; ++u)
-            m = fmin(m, pair_core<PREC>(st, ts, tl + (sub + ((k0 + u) << log2L)) * REC, eps2));
-        } else {
-          Sums<R> gs; // group sums, set by the group's first pair
-          m = pair_core<PREC, true>(st, gs, tl + (sub + (k0 << log2L)) * REC, eps2);
-#pragma unroll
-          for (int u = 1; u < kGroup; ++u)
-            m = fmin(m, pair_core<PREC>(st, gs, tl + (sub + ((k0 + u) << log2L)) * REC, eps2));
-          fold_or_add(gs, ts, t, m < gbest);
-        }
-        if (m < gbest) {
-          gbest = m;
-          grp = jbase + sub + (k0 << log2L);
-        }
-        if constexpr (NBL) nbm |= (m < h2 ? 1u : 0u) << (k0 / kGroup);
-      }
-      if constexpr (NBL) {
-        while (nbm) { // rare: append the neighbours of the flagged groups
-          const int g = __builtin_ctz(nbm);
-          nbm &= nbm - 1u;
-          for (int u = 0; u < kGroup; ++u) {
-            const int jj = sub + ((g * kGroup + u) << log2L);
-            if (r2_of<PREC>(st, tl + jj * REC) < h2) nb_append(nb_count, nb_slot, row, jbase + jj);
-          }
-        }
-      }
+      grouped<false>(tl, jbase, eps2, nb_count, nb_slot);
     }
     fold(ts, t);
   }
 
+  template <bool SELF>
+  __device__ __forceinline__ void grouped(const float4 *__restrict__ tl, int jbase, R eps2,
+                                          int *__restrict__ nb_count, int *__restrict__ nb_slot) {
+    const int o = slot - jbase; // own slot relative to the tile
+    unsigned nbm = 0u;
+    for (int k0 = 0; k0 < K; k0 += kGroup) {
+      R m = R(INFINITY);
+      if constexpr (PREC == G6MI_PREC_FP64) {
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+          const int jj = sub + ((k0 + u) << log2L);
+          m = fmin(m, pair_core<PREC, false, SELF>(st, ts, tl + jj * REC, eps2, jj == o));
+        }
+      } else {
+        Sums<R> gs; // group sums, set by the group's first pair
+        m = pair_core<PREC, true, SELF>(st, gs, tl + (sub + (k0 << log2L)) * REC, eps2, sub + (k0 << log2L) == o);
+#pragma unroll
+        for (int u = 1; u < kGroup; ++u) {
+          const int jj = sub + ((k0 + u) << log2L);
+          m = fmin(m, pair_core<PREC, false, SELF>(st, gs, tl + jj * REC, eps2, jj == o));
+        }
+        fold_or_add(gs, ts, t, m < gbest);
+      }
+      if (m < gbest) {
+        gbest = m;
+        grp = jbase + sub + (k0 << log2L);
+      }
+      if constexpr (NBL) nbm |= (m < h2 ? 1u : 0u) << (k0 / kGroup);
+    }
+    if constexpr (NBL) {
+      while (nbm) { // rare: append the neighbours of the flagged groups
+        const int g = __builtin_ctz(nbm);
+        nbm &= nbm - 1u;
+        for (int u = 0; u < kGroup; ++u) {
+          const int jj = sub + ((g * kGroup + u) << log2L);
+          if ((!SELF || jj != o) && r2_of<PREC>(st, tl + jj * REC) < h2) nb_append(nb_count, nb_slot, row, jbase + jj);
+        }
+      }
+    }
+  }
+
   __device__ __forceinline__ void resolve(const float4 *__restrict__ src, int base) {
-    resolve_group<PREC>(st, grp, L, src, base, ebest, eslot);
+    resolve_group<PREC>(st, grp, L, src, base, ebest, eslot, slot);
   }
 
   // Add the L lane totals of each i-particle through `red` (LDS, [9][kWG]

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kWG, wide_waves<PREC>()) void force_wide(ForceArgs 
     }
     __syncthreads();
     // DS: every group goes straight to the float64 totals (see WideLanes::tile)
-    w.template tile<PREC == G6MI_PREC_DS>(tile, jbase, cnt, eps2, a.nb_count, a.nb_slot);
+    w.template tile<PREC == G6MI_PREC_DS, true>(tile, jbase, cnt, eps2, a.nb_count, a.nb_slot);
   }
   // exact slot of the fast-path nearest neighbours: their groups are
   // re-read from global memory (every slot is < nj)
