@@ -6,15 +6,16 @@
 //                         j-splits) and a flat list of work items
 //                         (cluster, i-block, j-split); the other workgroups
 //                         clear the per-row counters of the calculation.
-//   batch_kernel       -- persistent workgroups take items from a work queue
-//                         (one atomic counter).  An item predicts its j-tiles
+//   batch_kernel       -- persistent workgroups take items from work queues
+//                         (a static first round, then eight atomic counters).
+//                         An item predicts its j-tiles
 //                         straight into LDS from the float64 j-memory (the
 //                         predictor of Sec. 2.2 fused into the tile load),
 //                         runs the interaction of Sec. 2.3 on them and stores
 //                         its split partials.
-//   batch_reduce       -- one workgroup per i-block adds the partials of all
-//                         its splits in a fixed order and writes the results
-//                         (the reduction of Sec. 2.3).
+//   batch_reduce       -- workgroups over parts of the i-blocks add the
+//                         partials of all splits in a fixed order and write
+//                         the results (the reduction of Sec. 2.3).
 //   batch_nb_exact     -- exact neighbour lists for overflowed i-particles.
 //
 // Each cluster is what the paper's library evaluates per call; batching them
