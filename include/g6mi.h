@@ -479,6 +479,7 @@ int g6calc_lasthalf2_(const int *id, const int *nj, const int *ni,
                       const double vi[][3], const double *eps2,
                       const double h2[], double acc[][3], double jerk[][3],
                       double pot[], int nnbindex[]);
+int g6_nearest_neighbour_(const int *id, const int *ni, int nnbindex[], double r2nn[]);
 int g6_read_neighbour_list_(const int *id);
 int g6_get_neighbour_list_(const int *id, const int *ipipe,
                            const int *maxlength, int *nblen, int nbl[]);

@@ -1803,6 +1803,9 @@ G6MI_API int g6calc_lasthalf2_(const int *id, const int *nj, const int *ni, cons
                                double pot[], int nnbindex[]) {
   return g6calc_lasthalf2(*id, *nj, *ni, index, xi, vi, *eps2, h2, acc, jerk, pot, nnbindex);
 }
+G6MI_API int g6_nearest_neighbour_(const int *id, const int *ni, int nnbindex[], double r2nn[]) {
+  return g6_nearest_neighbour(*id, *ni, nnbindex, r2nn);
+}
 G6MI_API int g6_read_neighbour_list_(const int *id) { return g6_read_neighbour_list(*id); }
 G6MI_API int g6_get_neighbour_list_(const int *id, const int *ipipe, const int *maxlength,
                                     int *nblen, int nbl[]) {
