@@ -133,3 +133,18 @@ def test_fortran_aliases_take_addresses(g6):
     op.argtypes = [ctypes.POINTER(ctypes.c_int)]
     bad = ctypes.c_int(-5)
     assert op(ctypes.byref(bad)) == g6.EINVAL
+
+
+def test_nearest_neighbour_alias_forwards(g6):
+    """The Fortran alias reads id and ni by address and returns what the C
+    call returns (here: the error for a handle that is not open)."""
+    lib = ctypes.CDLL(g6.LIB_PATH)
+    f = lib.g6_nearest_neighbour_
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), ctypes.c_void_p, ctypes.c_void_p]
+    nnb = np.zeros(4, dtype=np.int32)
+    r2 = np.zeros(4)
+    for hid in (0, 7, -3):
+        want = g6.g6_nearest_neighbour(hid, 4, nnb, r2)
+        got = f(ctypes.byref(ctypes.c_int(hid)), ctypes.byref(ctypes.c_int(4)), nnb.ctypes.data, r2.ctypes.data)
+        assert got == want and got < 0
