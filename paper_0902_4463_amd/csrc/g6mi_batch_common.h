@@ -96,11 +96,12 @@ __device__ __forceinline__ int reduce_parts(int nib, int grid, int cap) {
 // of two); parts from P on are empty.  Every thread of the workgroup calls
 // it with the same arguments; epi(row, sum) runs on the lane that wrote row
 // `row`, after the write, with the row's sums (acc xyz, jerk xyz, sum m/r).
-// Returns the status flags of this thread's rows.
-template <class Epi>
+// ONE: the batch is one cluster (cluster 0), whose i-block table need not be
+// read.  Returns the status flags of this thread's rows.
+template <bool ONE = false, class Epi>
 __device__ __forceinline__ int reduce_iblock(const BatchArgs &b, int ibg, int part, int nparts, Epi &&epi) {
   const int tid = threadIdx.x;
-  const int c = __builtin_amdgcn_readfirstlane(b.ib_cl[ibg]);
+  const int c = ONE ? 0 : __builtin_amdgcn_readfirstlane(b.ib_cl[ibg]);
   const g6mi_cluster d = b.cl[c];
   const BatchPlan p = b.plan[c];
   const int ib = ibg - p.ib0;

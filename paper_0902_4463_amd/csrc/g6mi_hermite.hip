@@ -76,11 +76,16 @@ __global__ __launch_bounds__(256) void hs_select_kernel(HermiteArgs h) {
   const int tid = threadIdx.x;
   const int k = blockIdx.x * 256 + tid;
   HermiteCtl *ctl = h.ctl;
+  // both keys read with the phase, not after it (one dependent load fewer)
   const int ph = ctl->phase;
-  const double tb = key_value(ctl->key[ph]);
+  const unsigned long long k0 = ctl->key[0], k1 = ctl->key[1];
+  const double tb = key_value(ph ? k1 : k0);
   const bool go = tb <= ctl->t_end;
   const double tn = k < h.n ? h.jm.t[k] + h.dt[k] : INFINITY;
   const bool act = go && k < h.n && tn == tb;
+  // the active particles' loads go out before the block-wide steps below
+  double xp[3], vp[3];
+  if (act) predict_particle(h, k, tb, xp, vp);
   // the next block time, first part: the particles this step leaves alone
   key_min(act ? kKeyInf : order_key(tn), &ctl->key[ph ^ 1]);
   // slots of this block's active particles: wave counts, one atomic per block
@@ -96,8 +101,6 @@ __global__ __launch_bounds__(256) void hs_select_kernel(HermiteArgs h) {
   if (act) {
     int q = s_base + __popcll(m & ((1ull << lane) - 1ull));
     for (int w = 0; w < wave; ++w) q += s_wave[w];
-    double xp[3], vp[3];
-    predict_particle(h, k, tb, xp, vp);
     h.active[q] = k;
     for (int d = 0; d < 3; ++d) {
       h.xi[3 * static_cast<size_t>(q) + d] = xp[d];
@@ -121,7 +124,8 @@ __global__ __launch_bounds__(256) void hs_publish_kernel(HermiteArgs h, BatchArg
   if (threadIdx.x == 0) {
     HermiteCtl *ctl = h.ctl;
     const int ph = ctl->phase;
-    const double tb = key_value(ctl->key[ph]);
+    const unsigned long long k0 = ctl->key[0], k1 = ctl->key[1];
+    const double tb = key_value(ph ? k1 : k0);
     const bool go = tb <= ctl->t_end;
     g6mi_cluster d;
     d.joff = 0;
@@ -254,7 +258,7 @@ __global__ __launch_bounds__(256) void hs_correct_kernel(HermiteArgs h, BatchArg
   const int nib_total = b.work->nib;
   const int P = reduce_parts(nib_total, min(static_cast<int>(gridDim.x), kHsReduceWgs), 64);
   for (int u = blockIdx.x; u < nib_total * P; u += gridDim.x)
-    fl |= reduce_iblock(b, u / P, u % P, P, [&](int q, const double *sum) {
+    fl |= reduce_iblock<true>(b, u / P, u % P, P, [&](int q, const double *sum) {
       const unsigned long long key = order_key(tb + correct_particle(h, q, tb, sum));
       next = key < next ? key : next;
     });
