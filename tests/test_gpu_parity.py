@@ -125,6 +125,26 @@ def test_sizes_and_tails(g6, orc, sess, n, ni, prec):
     assert_parity(gpu, ref, jm, h2, prec, f"N={n} ni={ni}")
 
 
+@pytest.mark.parametrize("prec", ["ds", "fp64"])
+@pytest.mark.parametrize("ni,shape", [(300, (0, 0)), (40, (0, 0)), (1500, (512, 3)), (300, (64, 5))])
+def test_self_tiles_unsoftened(g6, orc, sess, prec, ni, shape):
+    """A random subset of the particles as the block, so that nearly every
+    full tile holds some lane's own slot (the grouped path with the own pair
+    left out per pair), without softening: the own pair would add an
+    infinite term, or be its own nearest neighbour and neighbour, if it were
+    not left out exactly."""
+    n = 4096
+    jm = workloads.random_cluster(n, seed=77)
+    slots = workloads.active_set(n, ni, seed=78)
+    eps2, h2 = 0.0, 0.05
+    ref = with_xp(orc, jm, oracle_eval(orc, jm, slots, eps2, h2))
+    sess.load(jm)
+    gpu = gpu_eval(sess, g6, jm, slots, ref, eps2, h2, prec, shape=shape)
+    assert np.all(np.isfinite(gpu["acc"])) and np.all(np.isfinite(gpu["jerk"])) and np.all(np.isfinite(gpu["pot"]))
+    assert np.all(gpu["nn_index"] != jm.index[slots])
+    assert_parity(gpu, ref, jm, h2, prec, f"self tiles eps=0 ni={ni} shape={shape}")
+
+
 @pytest.mark.parametrize("shape", [(1, 1), (1, 37), (4, 3), (64, 7), (256, 1), (8, 100), (2, 13), (128, 2),
                                    (512, 1), (512, 5)])
 def test_launch_shapes(g6, orc, sess, shape):
