@@ -201,6 +201,23 @@ def test_batch_parity(g6, sess, prec):
         assert rep["acc_max"] < 1e-12 and rep["pot_max"] < 1e-13
 
 
+def test_batch_of_many_clusters(g6, sess):
+    """More clusters than the plan takes in one chunk of 256 (700 small
+    clusters, N 16..160): the plan entries go through memory between its
+    passes, and the item and i-block tables span several chunks."""
+    import oracle
+    cb = small_batch(seed=47, nclusters=700, n_lo=16, n_hi=160)
+    xp, vp = predicted(oracle, cb)
+    xi, vi, h2 = i_block(cb, xp, vp)
+    ref = oracle_rows(oracle, cb, xp, vp, xi, vi, h2)
+    sess.load(cb.jm)
+    g6.check(sess.id, g6.g6mi_set_precision(sess.id, "ds"))
+    b = Batch(g6, cb, xi, vi, h2)
+    g6.check(sess.id, b.run(sess.id))
+    check_rows(g6, sess.id, b.fetch(), ref, cb, xp, xi, "700 clusters")
+    assert g6.g6mi_last_status(sess.id) & ~g6.FLAG_NB_OVERFLOW == 0
+
+
 TUNINGS = [dict(item_work=1, wide_min=1, wg_per_cu=1, max_split=1),
            dict(item_work=16, wide_min=100000, wg_per_cu=2, max_split=64),
            dict(item_work=2, wide_min=257, wg_per_cu=3, max_split=3),
