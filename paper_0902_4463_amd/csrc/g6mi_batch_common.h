@@ -1,7 +1,8 @@
 // Device pieces of the batched launch shared by the batch kernels
 // (g6mi_batch.hip) and the device-resident block steps (g6mi_hermite.hip):
 // the per-cluster launch plan and the reduction of one i-block's split
-// partials.
+// partials.  The plan functions also compile for the host, where a test
+// checks their invariants.
 
 #pragma once
 
@@ -14,7 +15,7 @@ namespace g6mi {
 // 256 and up to the item target (item_work * 128 lane-pairs, not below
 // kBatchMinIpw), so that one tile of a narrow block stays within the target.
 // The tile count is kept in per until the splits are chosen.
-__device__ __forceinline__ BatchPlan plan_shape(int ni, int nj, const BatchTune &t) {
+__host__ __device__ __forceinline__ BatchPlan plan_shape(int ni, int nj, const BatchTune &t) {
   BatchPlan pl{};
   int ipw = 1, l2 = 0;
   if (ni >= t.wide_min) {
@@ -37,7 +38,7 @@ __device__ __forceinline__ BatchPlan plan_shape(int ni, int nj, const BatchTune 
 
 // Lane-pairs of a shaped cluster (one tile costs a lane ipw pairs on a
 // narrow block, 512 on a wide one).
-__device__ __forceinline__ long long plan_work(const BatchPlan &pl) {
+__host__ __device__ __forceinline__ long long plan_work(const BatchPlan &pl) {
   return static_cast<long long>(pl.nib) * pl.per * pl.ipw;
 }
 
@@ -46,7 +47,7 @@ __device__ __forceinline__ long long plan_work(const BatchPlan &pl) {
 // kBatchMinIpw, with more lanes per i-particle: a lone block of 340 against
 // 32768 particles then runs as 11 blocks of 32 in 704 items instead of 2
 // blocks of 256 in 128 items.  Returns whether the shape changed.
-__device__ __forceinline__ bool plan_share(BatchPlan &pl, long long share, const BatchTune &t) {
+__host__ __device__ __forceinline__ bool plan_share(BatchPlan &pl, long long share, const BatchTune &t) {
   const int most = min(max(pl.per, 1), t.max_split);
   if (pl.nib == 0 || static_cast<long long>(pl.nib) * most >= share) return false;
   while (pl.ipw > kBatchMinIpw && static_cast<long long>(pl.nib) * most < share) {
@@ -59,13 +60,13 @@ __device__ __forceinline__ bool plan_share(BatchPlan &pl, long long share, const
 
 // Item target in lane-pairs: item_work * 128, lowered (down to one) until
 // the batch's work makes about one item per persistent workgroup.
-__device__ __forceinline__ long long plan_target(long long work, int grid, const BatchTune &t) {
+__host__ __device__ __forceinline__ long long plan_target(long long work, int grid, const BatchTune &t) {
   return max(1LL, min(static_cast<long long>(t.item_work) * 128, work / max(1, grid)));
 }
 
 // Tiles per split and split count of a shaped cluster for the item target,
 // at most max_split splits.
-__device__ __forceinline__ void plan_splits(BatchPlan &pl, long long target, const BatchTune &t) {
+__host__ __device__ __forceinline__ void plan_splits(BatchPlan &pl, long long target, const BatchTune &t) {
   const int ntiles = pl.per;
   int per = static_cast<int>(max(1LL, min(static_cast<long long>(max(ntiles, 1)), target / pl.ipw)));
   int nsplit = ntiles > 0 ? (ntiles + per - 1) / per : 1;
@@ -83,7 +84,7 @@ __device__ __forceinline__ void plan_splits(BatchPlan &pl, long long target, con
 // grid strides over whole i-blocks).  A part is a contiguous run of the
 // i-block's rows; more parts put more workgroups, and so more loads in
 // flight, on the split partials, whose long sums are bound by latency.
-__device__ __forceinline__ int reduce_parts(int nib, int grid, int cap) {
+__host__ __device__ __forceinline__ int reduce_parts(int nib, int grid, int cap) {
   int P = 1;
   while (2 * P <= min(cap, 64) && static_cast<long long>(nib) * (2 * P) <= grid) P <<= 1;
   return P;
