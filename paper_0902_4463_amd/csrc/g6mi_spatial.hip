@@ -8,11 +8,21 @@
 // that a tile of 256 consecutive records and a workgroup's 512 i-particles
 // each occupy a compact box.  For a tile whose box is farther from the
 // i-box than K times the tile's own radius r_t, both sides are re-expressed
-// relative to the tile's centre c (a double-single difference per record and
-// per i-particle, once per tile) and the pairs use float32 differences of
-// those small coordinates.  With |x_j - c| <= r_t <= |x_j - x_i| / K the
-// separation error stays below 2 (1 + 1/K) units of the float32 rounding
-// (the double-single form's is below 2); nearer tiles, tiles holding an
+// relative to the tile's centre c and the pairs use float32 differences of
+// those small coordinates.
+//
+// Error of the far separation.  A = x_j - c and B = x_i - c are formed once
+// per tile (per record and per i-particle, not per pair) in float64 from the
+// double-single values, where hi + lo and c_hi + c_lo are exact, and rounded
+// once to float32; the pair then takes d = fl(A' - B').  With |A| <= r_t and
+// the boxes' gap g >= K r_t (so |D| >= g >= K r_t, D = x_j - x_i),
+//   |d - D| <= u (|A| + |B| + |D|) <= u (r_t + (r_t + |D|) + |D|)
+//            <= 2 (1 + 1/K) u |D|,   u = 2^-24,
+// against 2 u |D| for Eq. (3) (both up to O(u^2) terms, and both relative to
+// the double-single positions themselves).  The tile and i-boxes are
+// rounded outwards from hi + lo, so that they contain the double-single
+// positions and the computed gap never exceeds the true distance by more
+// than its own float32 rounding.  Nearer tiles, tiles holding an
 // i-particle's own record and ragged tiles take the double-single path.
 //
 //   sp_init_kernel, sp_bbox_kernel    bounding box of the predicted j (hi parts)
@@ -177,15 +187,25 @@ __global__ __launch_bounds__(256) void sp_igather_kernel(int ni, int nj, const i
   spos[d] = (slot >= 0 && slot < nj) ? inv[slot] : -1;
 }
 
-// One workgroup per tile of sorted records: box of the hi parts, centre c
-// (float64 midpoint, split double-single), radius r_t = the largest
-// |(x_hi - c_hi) + (x_lo - c_lo)| computed as on the far path, rounded up.
+// Outward float32 bounds of a double-single value hi + lo (exact in float64):
+// down <= hi + lo <= up.
+__device__ __forceinline__ void ds_bounds(float hi, float lo, float &down, float &up) {
+  const double v = static_cast<double>(hi) + static_cast<double>(lo);
+  const float f = static_cast<float>(v);
+  down = static_cast<double>(f) > v ? nextafterf(f, -INFINITY) : f;
+  up = static_cast<double>(f) < v ? nextafterf(f, INFINITY) : f;
+}
+
+// One workgroup per tile of sorted records: the box of the double-single
+// positions (rounded outwards), its centre c (float64 midpoint, split
+// double-single) and the radius r_t >= max |x - c| over the tile, with x - c
+// formed in float64 from hi + lo and c_hi + c_lo (exact sums), rounded up.
 // tinfo[4 t .. 4 t + 3] = {c_hi, r_t}, {c_lo, 0}, {box min, 0}, {box max, 0}.
 __global__ __launch_bounds__(256) void sp_tile_kernel(int nj, const float4 *__restrict__ rec,
                                                       float4 *__restrict__ tinfo) {
   __shared__ unsigned s_box[6];
   __shared__ float s_c[6];
-  __shared__ float s_r[4];
+  __shared__ double s_r[4];
   const int tid = threadIdx.x;
   const int k = blockIdx.x * kTile + tid;
   const bool ok = k < nj;
@@ -196,9 +216,9 @@ __global__ __launch_bounds__(256) void sp_tile_kernel(int nj, const float4 *__re
   if (ok) {
     ph = rec[3 * static_cast<size_t>(k)];
     pl = rec[3 * static_cast<size_t>(k) + 1];
-    lo[0] = hi[0] = ph.x;
-    lo[1] = hi[1] = ph.y;
-    lo[2] = hi[2] = ph.z;
+    ds_bounds(ph.x, pl.x, lo[0], hi[0]);
+    ds_bounds(ph.y, pl.y, lo[1], hi[1]);
+    ds_bounds(ph.z, pl.z, lo[2], hi[2]);
   }
   box_reduce(lo, hi, s_box);
   __syncthreads();
@@ -209,20 +229,27 @@ __global__ __launch_bounds__(256) void sp_tile_kernel(int nj, const float4 *__re
     s_c[3 + tid] = static_cast<float>(c - static_cast<double>(chi));
   }
   __syncthreads();
-  float r = 0.0f;
+  double r = 0.0;
   if (ok) {
-    const float dx = (ph.x - s_c[0]) + (pl.x - s_c[3]);
-    const float dy = (ph.y - s_c[1]) + (pl.y - s_c[4]);
-    const float dz = (ph.z - s_c[2]) + (pl.z - s_c[5]);
-    r = sqrtf(dx * dx + dy * dy + dz * dz);
+    const float h[3] = {ph.x, ph.y, ph.z}, l[3] = {pl.x, pl.y, pl.z};
+    double r2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double a = (static_cast<double>(h[d]) + static_cast<double>(l[d])) -
+                       (static_cast<double>(s_c[d]) + static_cast<double>(s_c[3 + d]));
+      r2 += a * a;
+    }
+    r = sqrt(r2);
   }
   const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) r = fmaxf(r, __shfl_xor(r, off));
+  for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_xor(r, off));
   if (lane == 0) s_r[wave] = r;
   __syncthreads();
   if (tid == 0) {
-    const float rt = fmaxf(fmaxf(s_r[0], s_r[1]), fmaxf(s_r[2], s_r[3])) * (1.0f + 0x1p-20f);
+    const double rmax = fmax(fmax(s_r[0], s_r[1]), fmax(s_r[2], s_r[3]));
+    // rounded up, with a margin for the float64 rounding of the radius
+    const float rt = static_cast<float>(rmax) * (1.0f + 0x1p-20f);
     float4 *o = tinfo + 4 * static_cast<size_t>(blockIdx.x);
     o[0] = make_float4(s_c[0], s_c[1], s_c[2], rt);
     o[1] = make_float4(s_c[3], s_c[4], s_c[5], 0.0f);
@@ -254,18 +281,22 @@ __global__ __launch_bounds__(kWG, wide_waves<G6MI_PREC_DS>()) void force_spatial
   w.pos1 = v1 ? sp.spos[q1] : -1;
   const float eps2 = static_cast<float>(a.eps2);
 
-  // box of this workgroup's i-particles (hi parts)
+  // box of this workgroup's i-particles (double-single positions, rounded
+  // outwards)
   {
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
+      float dn, up;
       if (v0) {
-        lo[d] = fminf(lo[d], w.s0.xh[d]);
-        hi[d] = fmaxf(hi[d], w.s0.xh[d]);
+        ds_bounds(w.s0.xh[d], w.s0.xl[d], dn, up);
+        lo[d] = fminf(lo[d], dn);
+        hi[d] = fmaxf(hi[d], up);
       }
       if (v1) {
-        lo[d] = fminf(lo[d], w.s1.xh[d]);
-        hi[d] = fmaxf(hi[d], w.s1.xh[d]);
+        ds_bounds(w.s1.xh[d], w.s1.xl[d], dn, up);
+        lo[d] = fminf(lo[d], dn);
+        hi[d] = fmaxf(hi[d], up);
       }
     }
     __shared__ unsigned s_ibk[6];
@@ -315,18 +346,24 @@ __global__ __launch_bounds__(kWG, wide_waves<G6MI_PREC_DS>()) void force_spatial
     const float reach = G6MI_FAR_K * c_hi.w;
     const bool far = cnt == kTile && !any_self && g2 >= reach * reach;
     if (far) {
+      // x - c in float64 from the exact sums hi + lo and c_hi + c_lo, rounded
+      // once to float32 (the error bound in the header)
+      const double c64[3] = {static_cast<double>(c_hi.x) + static_cast<double>(c_lo.x),
+                             static_cast<double>(c_hi.y) + static_cast<double>(c_lo.y),
+                             static_cast<double>(c_hi.z) + static_cast<double>(c_lo.z)};
+      auto rel = [&](float h, float l, int d) {
+        return static_cast<float>((static_cast<double>(h) + static_cast<double>(l)) - c64[d]);
+      };
       {
         const float4 p = tile[tid * REC], q = tile[tid * REC + 1], v = tile[tid * REC + 2];
-        ftile[tid * FREC] = make_float4((p.x - c_hi.x) + (q.x - c_lo.x), (p.y - c_hi.y) + (q.y - c_lo.y),
-                                        (p.z - c_hi.z) + (q.z - c_lo.z), p.w);
+        ftile[tid * FREC] = make_float4(rel(p.x, q.x, 0), rel(p.y, q.y, 1), rel(p.z, q.z, 2), p.w);
         ftile[tid * FREC + 1] = make_float4(v.x, v.y, v.z, q.w);
       }
       IState<G6MI_PREC_FP32> f0, f1;
-      const float ch[3] = {c_hi.x, c_hi.y, c_hi.z}, cl[3] = {c_lo.x, c_lo.y, c_lo.z};
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        f0.x[d] = (w.s0.xh[d] - ch[d]) + (w.s0.xl[d] - cl[d]);
-        f1.x[d] = (w.s1.xh[d] - ch[d]) + (w.s1.xl[d] - cl[d]);
+        f0.x[d] = rel(w.s0.xh[d], w.s0.xl[d], d);
+        f1.x[d] = rel(w.s1.xh[d], w.s1.xl[d], d);
         f0.v[d] = w.s0.v[d];
         f1.v[d] = w.s1.v[d];
       }
