@@ -196,7 +196,8 @@ class BlockStepIntegrator:
         dt_new = np.sqrt(self.eta * num / np.maximum(den, 1e-300))
         old = s.dt[sel]
         new = old.copy()
-        shrink = dt_new < old
+        # halve while too long, never below dt_min
+        shrink = (dt_new < old) & (old > self.dt_min)
         while np.any(shrink):
             new[shrink] *= 0.5
             shrink = (dt_new < new) & (new > self.dt_min)

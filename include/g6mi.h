@@ -412,7 +412,7 @@ int g6mi_batch_autotune(int id, int ncl, const g6mi_cluster *cl,
  *
  * The client side of Sec. 2.1 (i-prediction, Hermite corrector, block time
  * steps) run on the GPU, so that a whole block step is one replayed graph
- * of five kernels with no host round trip.  The particles are j-slots
+ * of four kernels with no host round trip.  The particles are j-slots
  * 0 .. n-1 of handle id: their t, mass, x, v and index as last set (all t
  * equal); the integrator then owns those slots and updates them in place
  * (position, velocity, a/2, jerk/6, time) after every step.
@@ -424,7 +424,7 @@ int g6mi_batch_autotune(int id, int ncl, const g6mi_cluster *cl,
  * softening eps2 and neighbour radius^2 h2; the Makino-Aarseth corrector
  * gives x, v at t_b; the next step is Aarseth's sqrt(eta (|a||a2| + |j|^2) /
  * (|j||a3| + |a2|^2)) with a2 taken at the end of the step, halved while
- * too long (down to dt_min) and doubled (up to dt_max) only when t_b is a
+ * too long but never below dt_min, and doubled (up to dt_max) only when t_b is a
  * multiple of the doubled step; the first step is eta_s |a| / |j| rounded
  * down to a power of two in [dt_min, dt_max].
  *

@@ -345,7 +345,7 @@ __global__ __launch_bounds__(kWG) void batch_nb_exact_kernel(BatchArgs b) {
       return buf;
     };
     exact_list<PREC>(st, slot, h2, d.joff, d.joff + d.nj, jm.index, rec_of,
-                     b.fa.nb_slot + static_cast<size_t>(row) * kNbMax, s_cnt, s_keep);
+                     b.fa.nb_slot + static_cast<size_t>(row) * kNbMax, b.fa.nb_count + row, s_cnt, s_keep);
   }
 }
 

@@ -955,16 +955,20 @@ __device__ __forceinline__ void split_lane_map(int lane, int G, int &ioff, int &
 
 // Rebuild the list of one overflowed i-particle as the kNbMax smallest
 // particle indices among its neighbours in slots jlo .. jhi - 1, ascending
-// (the oracle's convention).  Called by a whole workgroup.  The neighbour
-// test is the one of the interaction kernels (same separation and r^2
-// arithmetic on the same records, fetched by rec_of(js, scratch)).  A
-// binary search on the index threshold T counts the neighbours with index
-// below T (indices biased to unsigned order); then the kNbMax of them below
-// the final T are collected and rank-sorted.
+// (the oracle's convention), and write its neighbour count to *cnt.  Called
+// by a whole workgroup.  The neighbour test is the one of the interaction
+// kernels (same separation and r^2 arithmetic on the same records, fetched
+// by rec_of(js, scratch)); count and list both come from this pass, so they
+// agree even where the interaction kernel's own test (on the spatial path, a
+// float32 separation relative to a tile centre) decided a pair at the
+// sphere's edge the other way.  A binary search on the index threshold T
+// counts the neighbours with index below T (indices biased to unsigned
+// order); then the kNbMax of them below the final T are collected and
+// rank-sorted.
 template <int PREC, class RecOf>
 __device__ void exact_list(const IState<PREC> &st, int slot, real_t<PREC> h2, int jlo, int jhi,
                            const int *__restrict__ jindex, RecOf rec_of, int *__restrict__ lst,
-                           unsigned &s_cnt, int *s_keep) {
+                           int *__restrict__ cnt, unsigned &s_cnt, int *s_keep) {
   const int tid = threadIdx.x;
   auto below = [&](unsigned long long T, bool collect) -> unsigned {
     __syncthreads();
@@ -987,12 +991,17 @@ __device__ void exact_list(const IState<PREC> &st, int slot, real_t<PREC> h2, in
     __syncthreads();
     return s_cnt;
   };
-  // smallest T with at least kNbMax neighbours below it
-  unsigned long long lo = 0ull, hi = 1ull << 32;
-  while (hi - lo > 1ull) {
-    const unsigned long long mid = (lo + hi) >> 1;
-    if (below(mid, false) >= static_cast<unsigned>(kNbMax)) hi = mid;
-    else lo = mid;
+  constexpr unsigned long long kAll = 1ull << 32;
+  const unsigned total = below(kAll, false);
+  // smallest T with at least kNbMax neighbours below it (all of them when
+  // there are no more than kNbMax)
+  unsigned long long lo = 0ull, hi = kAll;
+  if (total > static_cast<unsigned>(kNbMax)) {
+    while (hi - lo > 1ull) {
+      const unsigned long long mid = (lo + hi) >> 1;
+      if (below(mid, false) >= static_cast<unsigned>(kNbMax)) hi = mid;
+      else lo = mid;
+    }
   }
   const unsigned got = below(hi, true);
   const int n = got < static_cast<unsigned>(kNbMax) ? static_cast<int>(got) : kNbMax;
@@ -1002,6 +1011,7 @@ __device__ void exact_list(const IState<PREC> &st, int slot, real_t<PREC> h2, in
     for (int u = 0; u < n; ++u) r += (s_keep[u] < v) | ((s_keep[u] == v) & (u < tid));
     lst[r] = v;
   }
+  if (tid == 0) *cnt = static_cast<int>(total);
   __syncthreads(); // s_keep is reused by the next i-particle
 }
 

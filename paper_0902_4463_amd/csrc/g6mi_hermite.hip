@@ -226,11 +226,7 @@ __device__ __forceinline__ double correct_particle(const HermiteArgs &h, int q, 
   const double dt_new = sqrt(h.eta * num / fmax(den, 1e-300));
   const double old = h.dt[k];
   double nw = old;
-  if (dt_new < nw) {
-    do {
-      nw *= 0.5;
-    } while (dt_new < nw && nw > h.dt_min);
-  }
+  while (dt_new < nw && nw > h.dt_min) nw *= 0.5; // never below dt_min
   if (dt_new >= 2.0 * old && fmod(tb, 2.0 * old) == 0.0 && 2.0 * old <= h.dt_max) nw = 2.0 * old;
   h.jm.t[k] = tb;
   h.dt[k] = nw;

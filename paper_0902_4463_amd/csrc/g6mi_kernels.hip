@@ -252,7 +252,7 @@ __global__ __launch_bounds__(kWG) void nb_exact_kernel(ForceArgs a, const int *_
     real_t<PREC> h2;
     load_i<PREC>(st, a, i, true, slot, h2);
     exact_list<PREC>(st, slot, h2, 0, a.nj, jindex, rec_of, a.nb_slot + static_cast<size_t>(i) * kNbMax,
-                     s_cnt, s_keep);
+                     a.nb_count + i, s_cnt, s_keep);
   }
 }
 

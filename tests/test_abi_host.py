@@ -148,3 +148,51 @@ def test_nearest_neighbour_alias_forwards(g6):
         want = g6.g6_nearest_neighbour(hid, 4, nnb, r2)
         got = f(ctypes.byref(ctypes.c_int(hid)), ctypes.byref(ctypes.c_int(4)), nnb.ctypes.data, r2.ctypes.data)
         assert got == want and got < 0
+
+
+def test_header_compiles_as_c11_and_links(g6, tmp_path):
+    """A C11 translation unit that includes g6mi.h, takes the address of
+    every declared function (Fortran aliases included), checks the public
+    struct sizes and calls the GPU-free entry points by C and by Fortran
+    convention compiles warning-free under -pedantic, links against
+    libg6mi.so and runs."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    names = declared_functions()
+    table = ",\n    ".join(f"(fn){n}" for n in names)
+    src = f"""
+#include "g6mi.h"
+#include <stdio.h>
+#include <string.h>
+typedef void (*fn)(void);
+_Static_assert(sizeof(g6mi_cluster) == 32, "g6mi_cluster is 32 bytes");
+_Static_assert(sizeof(g6mi_batch_tuning) == 16, "g6mi_batch_tuning is 16 bytes");
+static const fn every[] = {{
+    {table}
+}};
+int main(void) {{
+  int i, n = 0, id = -5;
+  for (i = 0; i < (int)(sizeof every / sizeof every[0]); ++i) n += every[i] != 0;
+  /* C and Fortran call sites of calls that need no GPU */
+  if (g6mi_nb_max() != G6MI_NB_MAX) return 2;
+  if (g6_npipes_() != g6_npipes()) return 3;
+  if (g6_open_(&id) != G6MI_EINVAL || g6_open(-5) != G6MI_EINVAL) return 4;
+  if (g6mi_last_error(-5) == 0 || strlen(g6mi_last_error(-5)) == 0) return 5;
+  printf("%d\\n", n);
+  return 0;
+}}
+"""
+    c = tmp_path / "abi_check.c"
+    c.write_text(src)
+    exe = tmp_path / "abi_check"
+    libdir = os.path.dirname(g6.LIB_PATH)
+    cmd = [cc, "-std=c11", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", os.path.join(ROOT, "include"),
+           str(c), "-o", str(exe), "-L", libdir, "-lg6mi", f"-Wl,-rpath,{libdir}"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, (r.returncode, r.stderr)
+    assert int(r.stdout.strip()) == len(names)

@@ -78,3 +78,38 @@ def test_small_plummer_conserves_energy_and_momentum():
     assert abs((e1 - e0) / e0) < 1e-6
     # individual steps break exact momentum conservation only at the integration-error level
     assert np.allclose((st.m[:, None] * st.v).sum(axis=0), p0, atol=1e-8)
+
+
+class ConstantForce:
+    """Backend returning the same acceleration and jerk (|jerk| = 10^6 |a|)
+    at every call.  The corrector's derivatives are then a2 = -6 j / dt and
+    a3 = 12 j / dt^2, and the Aarseth step comes out near
+    sqrt(eta dt^2 / 48), far below dt_min once dt is there."""
+
+    def __init__(self, n):
+        self.n = n
+
+    def set_j(self, st, sel):
+        pass
+
+    def force(self, ti, index, xi, vi):
+        k = len(index)
+        return np.ones((k, 3)), np.full((k, 3), 1e6), -np.ones(k)
+
+
+def test_step_never_drops_below_dt_min():
+    """A particle at dt_min whose Aarseth step is shorter still stays at
+    dt_min: the step is halved only while it is above dt_min."""
+    x = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0]])
+    st = HermiteState(x, np.zeros((2, 3)), np.ones(2))
+    dt_min = 2.0 ** -20
+    # first step eta_s |a| / |jerk| = 1e-4, quantised to 2^-14
+    it = BlockStepIntegrator(st, ConstantForce(2), eta=0.01, eta_s=100.0, dt_max=2.0 ** -3, dt_min=dt_min)
+    assert np.all(st.dt == 2.0 ** -14)
+    times = [it.time]
+    for _ in range(12):
+        it.step()
+        times.append(it.time)
+        assert np.all(st.dt >= dt_min), st.dt
+    assert np.all(st.dt == dt_min)
+    assert np.all(np.diff(times)[-5:] == dt_min)
