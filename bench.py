@@ -66,6 +66,17 @@ def profiled_traffic():
     return float(vals["traffic_bytes_per_launch:".rstrip(":")])
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -83,8 +94,13 @@ def parse():
     ap.add_argument("--no-neighbour-lists", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target oracle time of the CPU baseline")
     ap.add_argument("--shape", default=None, help="i_per_group,j_splits override")
-    ap.add_argument("--sweep", default=None,
-                    help="comma-separated k: also time active blocks of 2^k against all N (DS, FP32, FP64)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the float32, Eq. (3)-everywhere and no-neighbour-list runs")
+    ap.add_argument("--no-host-path", action="store_true",
+                    help="skip the host-array g6calc_firsthalf/lasthalf timing")
+    ap.add_argument("--sweep", default="0,4,8,12,16,20",
+                    help="comma-separated k: also time active blocks of 2^k against all N (DS, FP32, FP64); "
+                         "'none' to skip; a block of all N reuses the headline and variant runs")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-cluster workload")
     ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--tune-cache", default=None, help="tuning cache file of the batched launch")
@@ -279,23 +295,26 @@ def main():
             log(f"[bench] {variant} warmup {w + 1}/{warmup} done")
         g6.check(hid, g6.g6mi_enable_timing(hid, 1))
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
+        # one event per step boundary on the launch stream: the mean over the
+        # timed region, and the median and minimum of the single steps
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        evs[0].record(stream)
         w0 = time.perf_counter()
-        for _ in range(steps):
+        for k in range(steps):
             step()
-        e1.record(stream)
+            evs[k + 1].record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
-        ms = e0.elapsed_time(e1)
+        ms = evs[0].elapsed_time(evs[-1])
+        per_step = [evs[k].elapsed_time(evs[k + 1]) for k in range(steps)]
         tot = g6.g6mi_timing_totals(hid)
         g6.check(hid, g6.g6mi_enable_timing(hid, 0))
         shape = g6.g6mi_get_shape(hid)
         res = {k: v.cpu().numpy().copy() for k, v in out.items()}
         log(f"[bench] {variant}: {steps} steps in {ms:.1f} ms (wall {wall * 1e3:.1f} ms), "
             f"force kernel {tot['force_ms'] / max(1, tot['count']):.3f} ms avg, shape {shape}")
-        return dict(ms_per_step=ms / steps, force_ms=tot["force_ms"] / max(1, tot["count"]),
+        return dict(ms_per_step=ms / steps, ms_median=float(np.median(per_step)), ms_min=float(min(per_step)),
+                    force_ms=tot["force_ms"] / max(1, tot["count"]),
                     predict_ms=tot["predict_ms"] / max(1, tot["count"]),
                     reduce_ms=tot["reduce_ms"] / max(1, tot["count"]), shape=shape, res=res,
                     wall_s=wall)
@@ -317,14 +336,81 @@ def main():
                             else "force_kernel") + f"<{args.variant}>", flop_per_pair=FLOP_PER_PAIR,
                     pairs_per_launch=pairs, avg_launch_ms=round(main_run["force_ms"], 4))
 
+    def variant_entry(r, peak_key=None):
+        f_tf = FLOP_PER_PAIR * pairs / (r["force_ms"] * 1e-3) / 1e12
+        e = dict(value=pairs / (r["ms_per_step"] * 1e-3), unit="pairs/s", ms_per_step=round(r["ms_per_step"], 3),
+                 ms_median=round(r["ms_median"], 3), ms_min=round(r["ms_min"], 3),
+                 force_ms=round(r["force_ms"], 3), achieved_tflops=round(f_tf, 3),
+                 frac_fp32_peak=round(f_tf / PEAK_FP32_TFLOPS, 4), shape=r["shape"], res=r["res"],
+                 predict_ms=round(r["predict_ms"], 4), reduce_ms=round(r["reduce_ms"], 4))
+        if peak_key == "fp64":
+            e["frac_fp64_peak"] = round(f_tf / PEAK_FP64_TFLOPS, 4)
+        return e
+
+    # the other precision variants and the paper's two ablations on the same
+    # workload: float32 and float64 arithmetic; double-single with Eq. (3) on
+    # every tile (no spatial ordering, no float32 far tiles); double-single
+    # without neighbour lists (Sec. 4)
     variants = {}
-    if not args.no_fp64 and args.variant != "fp64":
-        fp = run("fp64", max(1, args.steps // 2), 1)
-        f_tf = FLOP_PER_PAIR * pairs / (fp["force_ms"] * 1e-3) / 1e12
-        variants["fp64"] = dict(value=pairs / (fp["ms_per_step"] * 1e-3), unit="pairs/s",
-                                ms_per_step=round(fp["ms_per_step"], 3), force_ms=round(fp["force_ms"], 3),
-                                achieved_tflops=round(f_tf, 3), frac_fp64_peak=round(f_tf / PEAK_FP64_TFLOPS, 4),
-                                frac_fp32_peak=round(f_tf / PEAK_FP32_TFLOPS, 4), res=fp["res"])
+    abl_steps = max(1, args.steps // 2)
+    if args.variant == "ds":
+        if not args.no_fp64:
+            variants["fp64"] = variant_entry(run("fp64", abl_steps, 1), "fp64")
+        if not args.no_variants:
+            variants["fp32"] = variant_entry(run("fp32", abl_steps, 1))
+            g6.check(hid, g6.g6mi_set_spatial(hid, 0))
+            variants["ds_eq3"] = variant_entry(run("ds", abl_steps, 1))
+            variants["ds_eq3"]["note"] = "double-single, Eq. (3) on every tile: spatial ordering and far tiles off"
+            g6.check(hid, g6.g6mi_set_spatial(hid, 1))
+            if not args.no_neighbour_lists:
+                g6.check(hid, g6.g6mi_set_neighbour_lists(hid, False))
+                variants["ds_no_lists"] = variant_entry(run("ds", abl_steps, 1))
+                variants["ds_no_lists"]["note"] = "double-single without neighbour lists"
+                g6.check(hid, g6.g6mi_set_neighbour_lists(hid, True))
+            g6.check(hid, g6.g6mi_set_precision(hid, args.variant))
+    elif not args.no_fp64 and args.variant != "fp64":
+        variants["fp64"] = variant_entry(run("fp64", abl_steps, 1), "fp64")
+    ablations = None
+    if "ds_eq3" in variants or "ds_no_lists" in variants:
+        ablations = {}
+        if "ds_eq3" in variants and "fp32" in variants:
+            # Sec. 1 and 2.3: double-single costs little over plain float32
+            ablations["ds_eq3_over_fp32"] = round(variants["ds_eq3"]["force_ms"] / variants["fp32"]["force_ms"], 4)
+            ablations["ds_over_fp32"] = round(main_run["force_ms"] / variants["fp32"]["force_ms"], 4)
+        if "ds_no_lists" in variants:
+            # Sec. 4: the cost of building neighbour lists
+            ablations["lists_on_over_off"] = round(main_run["force_ms"] / variants["ds_no_lists"]["force_ms"], 4)
+
+    # the GRAPE calling sequence on the host: g6calc_firsthalf -> lasthalf2
+    # with the i-block in host memory (PCIe both ways), then the neighbour
+    # lists read back
+    host_path = None
+    if not args.no_host_path:
+        g6.check(hid, g6.g6mi_set_precision(hid, args.variant))
+        h_idx = jm.index[slots]
+        h_xi, h_vi = np.ascontiguousarray(jm.x[slots]), np.ascontiguousarray(jm.v[slots])
+        h_h2 = np.full(ni, h2)
+        h_out = (np.empty((ni, 3)), np.empty((ni, 3)), np.empty(ni), np.empty(ni, dtype=np.int32))
+        times, nb_times = [], []
+        for rep in range(3):
+            torch.cuda.synchronize()
+            w0 = time.perf_counter()
+            g6.check(hid, g6.g6calc_firsthalf(hid, n, ni, h_idx, h_xi, h_vi, None, None, None, eps2, h_h2))
+            g6.check(hid, g6.g6calc_lasthalf2(hid, n, ni, h_idx, h_xi, h_vi, eps2, h_h2, *h_out))
+            w1 = time.perf_counter()
+            g6.check(hid, g6.g6_read_neighbour_list(hid))
+            w2 = time.perf_counter()
+            if rep > 0:  # the first call sizes the host staging buffers
+                times.append((w1 - w0) * 1e3)
+                nb_times.append((w2 - w1) * 1e3)
+        host_path = dict(firsthalf_to_lasthalf_ms=round(float(np.median(times)), 3),
+                         read_neighbour_list_ms=round(float(np.median(nb_times)), 3),
+                         device_step_ms=round(main_run["ms_per_step"], 3),
+                         pairs_per_s=pairs / (np.median(times) * 1e-3),
+                         note="host wall time of one call with host arrays: i-block upload, prediction, "
+                              "interaction, reduction and the results' download; median of 2 calls")
+        log(f"[bench] host path: firsthalf->lasthalf {host_path['firsthalf_to_lasthalf_ms']} ms, "
+            f"read_neighbour_list {host_path['read_neighbour_list_ms']} ms")
 
     # accuracy of a sample against the oracle, and the oracle's own rate
     cpu = None
@@ -348,11 +434,28 @@ def main():
         ref = oracle.force(xp, vp, jm.m, jm.index, jm.x[s], jm.v[s], jm.index[s], eps2, h2, conditioning=True)
         cs = time.perf_counter() - c0
         cpu_rate = ns * n / cs
+        # one thread on a fixed slice: the first 2^10 i of the sample against
+        # the first 2^16 j-slots
+        nj1 = min(n, 2 ** 16)
+        s1 = s[: min(len(s), 2 ** 10)]
+        oracle.set_threads(1)
+        try:
+            c1 = time.perf_counter()
+            oracle.force(xp[:nj1], vp[:nj1], jm.m[:nj1], jm.index[:nj1], jm.x[s1], jm.v[s1], jm.index[s1], eps2, h2)
+            one_thread = len(s1) * nj1 / (time.perf_counter() - c1)
+        finally:
+            oracle.set_threads(threads)
         cpu = dict(value=cpu_rate, unit="pairs/s", gflops=round(cpu_rate * FLOP_PER_PAIR / 1e9, 3),
                    cores=threads, affinity_cpus=len(os.sched_getaffinity(0)), kind="oracle",
-                   seconds=round(cs, 2),
+                   cpu_model=cpu_model(), seconds=round(cs, 2),
                    sample=f"{ns} of the {ni} active i-particles (seeded) against all {n} j-particles; "
-                          f"float64 C oracle, OpenMP over i")
+                          f"float64 C oracle, OpenMP over i",
+                   one_thread_pairs_per_s=one_thread,
+                   one_thread_slice=f"{len(s1)} i x {nj1} j, 1 thread",
+                   full_step_seconds=round(pairs / cpu_rate, 1),
+                   full_step_seconds_kind="extrapolated" if ns < ni else "measured",
+                   full_step_note=f"oracle time for all {ni} x {n} pairs: the sample's time scaled linearly "
+                                  f"in the number of i-particles (each i-particle's sum is independent)")
         accuracy = {}
         for name, res in [(args.variant, main_run["res"])] + [(k, v["res"]) for k, v in variants.items()]:
             gpu = dict(acc=res["acc"][pick], jerk=res["jerk"][pick], pot=res["pot"][pick])
@@ -367,10 +470,22 @@ def main():
         v.pop("res", None)
 
     sweep = None
-    if args.sweep:
+    if args.sweep and args.sweep != "none":
         sweep = []
         for k in (int(q) for q in args.sweep.split(",")):
             nk = 2 ** k
+            if nk == ni == n and args.variant == "ds" and "fp32" in variants and "fp64" in variants:
+                # all particles active: the headline and variant runs above
+                entry = dict(k=k, ni=nk, source="headline and variant runs")
+                for name, r in (("ds", dict(main_run, predict_ms=main_run["predict_ms"])), ("fp32", variants["fp32"]),
+                                ("fp64", variants["fp64"])):
+                    entry[name] = dict(ms_per_step=round(r["ms_per_step"], 4), force_ms=round(r["force_ms"], 4),
+                                       predict_ms=round(r["predict_ms"], 4), reduce_ms=round(r["reduce_ms"], 4),
+                                       pairs_per_s=float(nk) * n / (r["ms_per_step"] * 1e-3), shape=r["shape"])
+                sweep.append(entry)
+                continue
+            if nk > n:
+                continue
             sk = workloads.active_set(n, nk, seed=3)
             t_islot = torch.tensor(sk, device=dev)
             t_xi = t["x"][t_islot.long()].contiguous()
@@ -428,7 +543,9 @@ def main():
                     parallelism="single-gpu"),
         kernel_ms=dict(predict=round(main_run["predict_ms"], 4), force=round(main_run["force_ms"], 4),
                        reduce=round(main_run["reduce_ms"], 4)),
-        roofline=roofline, variants=variants, accuracy=accuracy, cpu_baseline=cpu, sweep=sweep, batched=batched,
+        ms_per_step_median=round(main_run["ms_median"], 4), ms_per_step_min=round(main_run["ms_min"], 4),
+        roofline=roofline, variants=variants, ablations=ablations, host_path=host_path, accuracy=accuracy,
+        cpu_baseline=cpu, sweep=sweep, batched=batched,
         device=dict(compute_units=info["compute_units"], clock_mhz=info["clock_mhz"],
                     name=torch.cuda.get_device_name(0)),
     )

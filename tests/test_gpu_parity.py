@@ -455,41 +455,82 @@ def test_config_c3_active_blocks(g6, orc, sess, k):
     assert rep["ok"] and nn["ok"]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "ds", "fp32"])
-def test_config_c5_precision_stress(g6, orc, sess, prec):
-    """Plummer N=2^18 with 5% hard-binary members, translated by 1e4,
-    eps = 0.  FP64 must meet the tolerances; DS and FP32 errors are
-    reported (the 2^-48 DS resolution at |x| = 1e4 is ~4e-11, comparable to
-    the tightest binaries' separations)."""
+@pytest.fixture(scope="module")
+def c5_case(orc):
+    """The config 5 system and the oracle on a sample of it: 1024 binary
+    members spread over the binaries' range of semi-major axes and 512
+    single stars."""
     jm = workloads.config_c5()
     n = jm.n
     eps2, h2 = jm.meta["eps2"], jm.meta["h2"]
-    device_jmem(g6, sess, jm)
-    g6.g6mi_set_precision(sess.id, prec)
-    g6.g6mi_set_shape(sess.id, 0, 0)
-    g6.g6_set_ti(sess.id, 0.0)
     nb_ = jm.meta["n_binaries"]
-    sample = np.concatenate([np.arange(0, 2 * nb_, 2 * nb_ // 128), workloads.active_set(n - 2 * nb_, 128, 5) + 2 * nb_])
-    sample = np.unique(sample).astype(np.int32)
-    _say(f"[C5] running {prec}")
-    dv = device_calc(g6, sess, n, sample, jm.x[sample], jm.v[sample], eps2, h2)
-    ref = orc.force(jm.x, jm.v, jm.m, jm.index, jm.x[sample], jm.v[sample], jm.index[sample], eps2, h2,
-                    conditioning=True)
-    gpu = dict(acc=dv["acc"], jerk=dv["jerk"], pot=dv["pot"])
-    finite = np.isfinite(gpu["acc"]).all(axis=1) & np.isfinite(gpu["jerk"]).all(axis=1)
-    rep = parity.force_report({k: np.where(np.isfinite(v), v, 0) for k, v in gpu.items()}, ref)
-    is_bin = jm.meta["is_binary"][sample]
-    ea, ej, ep = parity.rel_errors({k: np.where(np.isfinite(v), v, 0) for k, v in gpu.items()}, ref)
-    _say(f"[C5] {prec}: nonfinite={int((~finite).sum())} acc_max(bin)={ea[is_bin].max():.2e} "
-         f"acc_max(single)={ea[~is_bin].max():.2e} jerk_max={ej.max():.2e} pot_max={ep.max():.2e}")
+    members = np.arange(0, 2 * nb_, max(1, (2 * nb_) // 1024))[:1024]
+    singles = workloads.active_set(n - 2 * nb_, 512, 5) + 2 * nb_
+    slots = np.unique(np.concatenate([members, singles])).astype(np.int64)
+    ref = with_xp(orc, jm, oracle_eval(orc, jm, slots, eps2, h2))
+    return jm, slots, ref
+
+
+def c5_bins(jm, slots):
+    """Row groups of the config 5 sample: single stars, and binary members by
+    decade of the semi-major axis."""
+    nb_ = jm.meta["n_binaries"]
+    is_bin = slots < 2 * nb_
+    la = np.full(len(slots), np.nan)
+    la[is_bin] = np.log10(jm.meta["binary_a"][slots[is_bin] // 2])
+    groups = {"single": ~is_bin}
+    for lo in (-5, -4):
+        groups[f"binary a=1e{lo}..1e{lo + 1}"] = is_bin & (la >= lo) & (la < lo + 1)
+    return groups
+
+
+@pytest.mark.parametrize("prec", ["fp64", "ds", "fp32"])
+def test_config_c5_precision_stress(g6, orc, sess, c5_case, prec):
+    """Plummer N=2^18 with 5% hard-binary members, translated by 1e4,
+    eps = 0, neighbour radius 0.01 (the double-single resolution claim after
+    Eq. (3), and the neighbour lists of Sec. 4).  FP64 and DS must meet the
+    force tolerances on every single star, and give the oracle's nearest
+    neighbours and neighbour lists up to distance ties; FP64 also meets the
+    force tolerances on the binary members.  Errors are reported per group:
+    single stars and binary members by decade of the semi-major axis (DS
+    resolves |x| = 1e4 to about 2^-48 of it, 4e-11, against separations down
+    to ~1e-7 at pericentre).  FP32 (ulp 1e-3 at |x| = 1e4) is reported, not
+    graded."""
+    jm, slots, ref = c5_case
+    eps2, h2 = jm.meta["eps2"], jm.meta["h2"]
+    sess.load(jm)
+    _say(f"[C5] running {prec} on {len(slots)} i-particles")
+    gpu = gpu_eval(sess, g6, jm, slots, ref, eps2, h2, prec)
+    finite = np.isfinite(gpu["acc"]).all(axis=1) & np.isfinite(gpu["jerk"]).all(axis=1) & np.isfinite(gpu["pot"])
+    clean = {k: np.where(np.isfinite(gpu[k]), gpu[k], 0) for k in ("acc", "jerk", "pot")}
+    ea, ej, ep = parity.rel_errors(clean, ref)
+    xp = ref["_xp"]
+    nn = parity.nn_report(gpu["nn_index"], ref["nn_index"], ref["nn_r2"], xp, jm.index, ref["xi"])
+    nb = parity.nb_report(gpu["nb_count"], gpu["nb_list"], ref["nb_count"], ref["nb_list"], xp, jm.index,
+                          ref["xi"], h2)
+    groups = c5_bins(jm, slots)
+    for name, g in groups.items():
+        if not g.any():
+            continue
+        _say(f"[C5] {prec} {name} ({int(g.sum())}): nonfinite={int((~finite[g]).sum())} "
+             f"acc max={ea[g].max():.2e} median={np.median(ea[g]):.2e}  "
+             f"jerk max={ej[g].max():.2e} median={np.median(ej[g]):.2e}  pot max={ep[g].max():.2e}")
+    _say(f"[C5] {prec}: nn mismatch={nn['mismatch']} ties={nn['ties']} fail={nn['fail']}; "
+         f"neighbour lists fail={nb['fail']} ties={nb['ties']} overflow rows={nb['overflow_rows']}; "
+         f"oracle neighbours: {int(ref['nb_count'].sum())} in {int((ref['nb_count'] > 0).sum())} lists")
+    if prec == "fp32":
+        return
+    assert finite.all()
+    single = groups["single"]
+    keys = ("acc", "jerk", "pot", "acc_abs", "jerk_abs")
+    rep_single = parity.force_report({k: clean[k][single] for k in keys[:3]}, {k: ref[k][single] for k in keys})
+    assert rep_single["ok"], rep_single
+    assert nn["ok"], nn
+    assert nb["ok"] and nb["overflow_rows"] == 0, nb
+    assert int(ref["nb_count"].sum()) > 0
     if prec == "fp64":
-        assert finite.all() and rep["ok"], rep
-        nn = parity.nn_report(dv["nnb"], ref["nn_index"], ref["nn_r2"], jm.x, jm.index, jm.x[sample])
-        assert nn["ok"], nn
-    if prec == "ds":
-        assert finite.all()
-        # single stars are far from any partner: DS meets the tolerance there
-        assert ea[~is_bin].max() <= parity.TOL_ACC
+        rep = parity.force_report(clean, ref)
+        assert rep["ok"], rep
 
 
 @pytest.mark.parametrize("prec", ["ds", "fp64"])
