@@ -240,6 +240,17 @@ int g6mi_set_neighbour_lists(int id, int on);
  * or G6MI_ESTATE. */
 int g6mi_set_spatial(int id, int mode);
 
+/* Fused prediction for one-block calls (extension; on by default).  When the
+ * i-block of a calculation fits one workgroup of the narrow interaction
+ * kernel (at most 256 i-particles) and is not spatially ordered, that kernel
+ * predicts each j-tile into LDS from the float64 j-memory itself (Sec. 2.2,
+ * Eq. (1)-(2), fused into the tile load) instead of reading records written
+ * by a separate predictor launch, so the predicted records never go
+ * through HBM.  The arithmetic is the same either way and so are the
+ * results, bit for bit.  on = 0 always runs the separate predictor.
+ * Returns 0, G6MI_EINVAL or G6MI_ESTATE. */
+int g6mi_set_fused_predict(int id, int on);
+
 /* Override the launch shape of the interaction kernel: i-particles per
  * workgroup (a power of two, 1..512; 512 means two i-particles per lane,
  * 256 or fewer one per lane or several lanes per i-particle) and number of

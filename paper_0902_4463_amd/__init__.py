@@ -75,6 +75,7 @@ _SIGS = {
     "g6mi_set_neighbour_lists": (_i, [_i, _i]),
     "g6mi_set_shape": (_i, [_i, _i, _i]),
     "g6mi_set_spatial": (_i, [_i, _i]),
+    "g6mi_set_fused_predict": (_i, [_i, _i]),
     "g6mi_get_shape": (_i, [_i, _I]),
     "g6mi_enable_timing": (_i, [_i, _i]),
     "g6mi_last_timing": (_i, [_i, _D]),
@@ -280,6 +281,11 @@ def g6mi_set_neighbour_lists(id, on) -> int:
 def g6mi_set_spatial(id, mode) -> int:
     """0 off, 1 double-single blocks of at least 65536 (default), 2 every double-single calculation."""
     return _L().g6mi_set_spatial(id, int(mode))
+
+
+def g6mi_set_fused_predict(id, on) -> int:
+    """1: one-block calls predict their j-tiles inside the interaction kernel."""
+    return _L().g6mi_set_fused_predict(id, int(bool(on)))
 
 
 def g6mi_set_shape(id, i_per_group, j_splits) -> int:

@@ -87,6 +87,7 @@ struct Handle {
   int prec = G6MI_PREC_DS;
   bool nbl = true;
   int spatial = 1; // 0 off, 1 for large DS blocks, 2 always (DS)
+  bool fuse = true; // one-block calls predict their tiles in the interaction kernel
   int user_ipw = 0, user_nsplit = 0;
   int shape[4] = {0, 0, 0, 0};
   std::string err;
@@ -113,6 +114,12 @@ struct Handle {
 
   // work buffers
   DevBuf d_part, d_nnr2, d_nnslot, d_nbcount, d_nblist, d_flags, d_ovf;
+  // neighbour counters of the fused path: all zero between calculations
+  // (each reduction clears the rows it used); nbwork_ok is false until a
+  // new buffer has been cleared or after a calculation that did not reach
+  // its reduction
+  DevBuf d_nbwork;
+  bool nbwork_ok = false;
   DevBuf d_sp; // spatial ordering: one allocation cut into SpatialBufs
   SpatialBufs sp;
 
@@ -124,6 +131,9 @@ struct Handle {
   std::vector<int> c_index;
   hipStream_t c_stream = nullptr;
   ForceArgs c_args;        // interaction arguments of the last calculation
+  bool c_fused = false;    // ... made by force_fused (no predicted records kept)
+  double c_ti = 0.0;
+  int *c_flags = nullptr, *c_ovf = nullptr; // its status words and overflow queue
   int c_prec = G6MI_PREC_DS;
   bool c_nbl = true;
   bool c_have = false;     // a calculation was enqueued and not superseded
@@ -313,6 +323,7 @@ int ilog2(int v) {
 #endif
 constexpr int kWaveTarget = G6MI_WG_PER_CU;
 constexpr int kMinTiles = 8;
+constexpr int kOneSplits = 256;
 
 // Spatial ordering (g6mi_spatial.hip) for double-single blocks of at least
 // this many i-particles against at least two tiles (automatic mode).  The
@@ -329,9 +340,16 @@ bool use_spatial(const Handle &h, int ni, int nj) {
   return h.spatial == 1 && !h.user_ipw && ni >= kSpatialMinNi && nj >= 2 * kTile;
 }
 
-void choose_shape(Handle &h, int ni, int nj, int &ipw, int &nsplit) {
+// The predictor fused into the interaction (force_fused) for a call whose
+// block is one narrow i-block: every j-tile is then predicted once either
+// way, and the predicted records need not go through HBM.
+bool use_fused(const Handle &h, bool spatial, int ipw, int ni, int nj) {
+  return h.fuse && !spatial && ni > 0 && nj > 0 && ipw <= kWG && ni <= ipw;
+}
+
+void choose_shape(Handle &h, int ni, int nj, int &ipw, int &nsplit, bool may_order = true) {
   const int ntiles = (nj + kTile - 1) / kTile;
-  if (use_spatial(h, ni, nj)) ipw = 2 * kWG;
+  if (may_order && use_spatial(h, ni, nj)) ipw = 2 * kWG;
   else if (h.user_ipw) ipw = h.user_ipw;
   else if (ni >= 2 * kWG) ipw = 2 * kWG; // two i-particles per lane
   else {
@@ -347,6 +365,11 @@ void choose_shape(Handle &h, int ni, int nj, int &ipw, int &nsplit) {
     const long target = static_cast<long>(kWaveTarget) * std::max(1, h.ncu);
     nsplit = static_cast<int>(std::max(1L, (target + nib - 1) / std::max(1L, nib)));
     nsplit = std::max(1, std::min(nsplit, std::max(1, ntiles / kMinTiles)));
+    // one particle with the predictor fused in: the interaction streams the
+    // j-memory whatever the split count, and the reduction of 256 splits
+    // takes one round of loads where 512 take two (measured at 2^20 j:
+    // 25.3-26.3 against 26.4-27.1 us per call)
+    if (ipw == 1 && h.fuse) nsplit = std::min(nsplit, kOneSplits);
   }
   nsplit = std::min(nsplit, 4096);
 }
@@ -391,15 +414,64 @@ int ensure_spatial(Handle &h, int nj, int ni) {
   return 0;
 }
 
-int enqueue_calc(Handle &h, int nj, int ni, const int *d_islot, const double *d_xi,
-                 const double *d_vi, const double *d_h2, double eps2, double *d_acc,
-                 double *d_jerk, double *d_pot, int *d_nnb, double *d_r2nn, hipStream_t s) {
-  int rc = upload_dirty(h, s);
-  if (rc) return rc;
-  int ipw, nsplit;
-  choose_shape(h, ni, nj, ipw, nsplit);
+// Work buffers of one single-system calculation.
+struct CalcBufs {
+  void *pred = nullptr;                    // predicted j-records (not with the fused kernel)
+  double *part = nullptr, *nnr2 = nullptr; // split partials
+  int *nnslot = nullptr;
+  int *nbcount = nullptr, *nblist = nullptr;
+  int *flags = nullptr, *ovf = nullptr;    // status words, overflow queue
+  int *nbwork = nullptr;                   // fused kernel's neighbour counters
+  int nbwork_n = 0;                        // ... their number
+  bool nbwork_zero = false;                // nbwork is known to be all zero
+};
+
+// Bytes of the work buffers of a calculation of shape (ipw, nsplit) over
+// nj j-slots and ni i-particles, in the order and alignment of carve_bufs.
+size_t calc_bytes(int prec, bool fused, int nj, int ni, int nsplit) {
+  const size_t n = static_cast<size_t>(std::max(ni, 1)), ns = static_cast<size_t>(nsplit);
+  size_t b = 0;
+  auto add = [&](size_t x) { b += round_up(x, 256); };
+  add(fused ? 0 : std::max<size_t>(1, nj) * pred_record_bytes(prec));
+  add(ns * 7 * n * sizeof(double));
+  add(ns * n * sizeof(double));
+  add(ns * n * sizeof(int));
+  add(n * sizeof(int));
+  add(n * kNbMax * sizeof(int));
+  add(64);
+  add(2 * n * sizeof(int));
+  add(fused ? n * sizeof(int) : 0);
+  return b;
+}
+
+// The same buffers cut from one region of at least calc_bytes bytes.
+CalcBufs carve_bufs(void *base, int prec, bool fused, int nj, int ni, int nsplit) {
+  const size_t n = static_cast<size_t>(std::max(ni, 1)), ns = static_cast<size_t>(nsplit);
+  char *p = static_cast<char *>(base);
+  auto take = [&](size_t x) {
+    char *q = p;
+    p += round_up(x, 256);
+    return static_cast<void *>(q);
+  };
+  CalcBufs c;
+  c.pred = take(fused ? 0 : std::max<size_t>(1, nj) * pred_record_bytes(prec));
+  c.part = static_cast<double *>(take(ns * 7 * n * sizeof(double)));
+  c.nnr2 = static_cast<double *>(take(ns * n * sizeof(double)));
+  c.nnslot = static_cast<int *>(take(ns * n * sizeof(int)));
+  c.nbcount = static_cast<int *>(take(n * sizeof(int)));
+  c.nblist = static_cast<int *>(take(n * kNbMax * sizeof(int)));
+  c.flags = static_cast<int *>(take(64));
+  c.ovf = static_cast<int *>(take(2 * n * sizeof(int)));
+  c.nbwork = fused ? static_cast<int *>(take(n * sizeof(int))) : nullptr;
+  c.nbwork_n = fused ? static_cast<int>(n) : 0;
+  if (fused) c.pred = nullptr;
+  return c;
+}
+
+// The handle's own work buffers, grown as needed.
+int handle_bufs(Handle &h, bool fused, int nj, int ni, int nsplit, CalcBufs &c) {
   const size_t n = static_cast<size_t>(std::max(ni, 1));
-  HIPCHK(&h, ensure(h.d_pred, std::max<size_t>(1, nj) * pred_record_bytes(h.prec)));
+  if (!fused) HIPCHK(&h, ensure(h.d_pred, std::max<size_t>(1, nj) * pred_record_bytes(h.prec)));
   HIPCHK(&h, ensure(h.d_part, static_cast<size_t>(nsplit) * 7 * n * sizeof(double)));
   HIPCHK(&h, ensure(h.d_nnr2, static_cast<size_t>(nsplit) * n * sizeof(double)));
   HIPCHK(&h, ensure(h.d_nnslot, static_cast<size_t>(nsplit) * n * sizeof(int)));
@@ -407,14 +479,65 @@ int enqueue_calc(Handle &h, int nj, int ni, const int *d_islot, const double *d_
   HIPCHK(&h, ensure(h.d_nblist, n * kNbMax * sizeof(int)));
   HIPCHK(&h, ensure(h.d_flags, 64));
   HIPCHK(&h, ensure(h.d_ovf, 2 * n * sizeof(int)));
-  int *status = static_cast<int *>(h.d_flags.p); // zeroed by the predictor launch
+  c.pred = fused ? nullptr : h.d_pred.p;
+  c.part = static_cast<double *>(h.d_part.p);
+  c.nnr2 = static_cast<double *>(h.d_nnr2.p);
+  c.nnslot = static_cast<int *>(h.d_nnslot.p);
+  c.nbcount = static_cast<int *>(h.d_nbcount.p);
+  c.nblist = static_cast<int *>(h.d_nblist.p);
+  c.flags = static_cast<int *>(h.d_flags.p);
+  c.ovf = static_cast<int *>(h.d_ovf.p);
+  if (fused) {
+    const size_t before = h.d_nbwork.bytes;
+    HIPCHK(&h, ensure(h.d_nbwork, n * sizeof(int)));
+    if (h.d_nbwork.bytes != before) h.nbwork_ok = false;
+    c.nbwork = static_cast<int *>(h.d_nbwork.p);
+    c.nbwork_n = static_cast<int>(h.d_nbwork.bytes / sizeof(int));
+    c.nbwork_zero = h.nbwork_ok;
+  }
+  return 0;
+}
+
+// Enqueue one calculation on stream s.  scratch == nullptr: the handle's own
+// buffers (allocated as needed), the spatial ordering where it applies, and
+// the timing events.  Otherwise every work buffer is cut from `scratch`
+// (scratch_bytes long) and nothing is allocated: the calculation is not
+// spatially ordered and not timed, and j-split counts are lowered until the
+// buffers fit (G6MI_EINVAL when even one split does not).
+int enqueue_calc(Handle &h, int nj, int ni, const int *d_islot, const double *d_xi,
+                 const double *d_vi, const double *d_h2, double eps2, double *d_acc,
+                 double *d_jerk, double *d_pot, int *d_nnb, double *d_r2nn, hipStream_t s,
+                 void *scratch = nullptr, size_t scratch_bytes = 0) {
+  const bool noalloc = scratch != nullptr;
+  if (noalloc && !h.dirty.empty())
+    return fail(&h, G6MI_ESTATE, "j-particles set on the host wait for an upload, which needs staging memory");
+  if (!noalloc) {
+    int rc = upload_dirty(h, s);
+    if (rc) return rc;
+  }
+  int ipw, nsplit;
+  choose_shape(h, ni, nj, ipw, nsplit, !noalloc);
+  const bool spatial = !noalloc && use_spatial(h, ni, nj);
+  // one i-block of at most kWG: the interaction kernel predicts its tiles
+  const bool fused = use_fused(h, spatial, ipw, ni, nj);
+  CalcBufs c;
+  if (noalloc) {
+    while (nsplit > 1 && calc_bytes(h.prec, fused, nj, ni, nsplit) > scratch_bytes) nsplit = (nsplit + 1) / 2;
+    if (calc_bytes(h.prec, fused, nj, ni, nsplit) > scratch_bytes)
+      return fail(&h, G6MI_EINVAL, "calculation too large for the static scratch buffer (nj or ni too large)");
+    c = carve_bufs(scratch, h.prec, fused, nj, ni, nsplit);
+  } else {
+    int rc = handle_bufs(h, fused, nj, ni, nsplit, c);
+    if (rc) return rc;
+  }
+  int *status = c.flags; // cleared by the predictor launch, or by force_fused
 
   h.shape[0] = ipw;
   h.shape[1] = nsplit;
   h.shape[2] = kTile;
   h.shape[3] = ((ni + ipw - 1) / ipw) * nsplit;
   hipEvent_t *ev = nullptr;
-  if (h.timing && h.n_timed < kTimingRing) {
+  if (!noalloc && h.timing && h.n_timed < kTimingRing) {
     if (static_cast<size_t>(h.n_timed) == h.evs.size()) {
       std::array<hipEvent_t, 4> q{};
       for (auto &e : q) HIPCHK(&h, hipEventCreate(&e));
@@ -422,18 +545,20 @@ int enqueue_calc(Handle &h, int nj, int ni, const int *d_islot, const double *d_
     }
     ev = h.evs[h.n_timed].data();
   }
-  const bool spatial = use_spatial(h, ni, nj);
   if (spatial) {
     int rc2 = ensure_spatial(h, nj, ni);
     if (rc2) return rc2;
   }
+  if (fused) {
+    if (!c.nbwork_zero) HIPCHK(&h, launch_zero(c.nbwork_n, c.nbwork, s));
+    if (!noalloc) h.nbwork_ok = false; // until the reduction is enqueued
+  }
   if (ev) HIPCHK(&h, hipEventRecord(ev[0], s));
-  HIPCHK(&h, launch_predict(h.prec, nj, h.ti, h.jm, h.d_pred.p,
-                            static_cast<int *>(h.d_nbcount.p), ni, status, s));
-  if (spatial) HIPCHK(&h, launch_spatial_prep(h.sp, nj, ni, h.d_pred.p, d_xi, d_vi, d_h2, d_islot, s));
+  if (!fused) HIPCHK(&h, launch_predict(h.prec, nj, h.ti, h.jm, c.pred, c.nbcount, ni, status, s));
+  if (spatial) HIPCHK(&h, launch_spatial_prep(h.sp, nj, ni, c.pred, d_xi, d_vi, d_h2, d_islot, s));
   if (ev) HIPCHK(&h, hipEventRecord(ev[1], s));
   ForceArgs a;
-  a.jpred = h.d_pred.p;
+  a.jpred = c.pred;
   a.nj = nj;
   a.ni = ni;
   a.xi = d_xi;
@@ -443,20 +568,24 @@ int enqueue_calc(Handle &h, int nj, int ni, const int *d_islot, const double *d_
   a.eps2 = eps2;
   a.ipw = ipw;
   a.log2ipw = ilog2(ipw);
-  a.part = static_cast<double *>(h.d_part.p);
-  a.nn_r2 = static_cast<double *>(h.d_nnr2.p);
-  a.nn_slot = static_cast<int *>(h.d_nnslot.p);
-  a.nb_count = static_cast<int *>(h.d_nbcount.p);
-  a.nb_slot = static_cast<int *>(h.d_nblist.p);
+  a.part = c.part;
+  a.nn_r2 = c.nnr2;
+  a.nn_slot = c.nnslot;
+  a.nb_count = c.nbcount;
+  a.nb_slot = c.nblist;
   if (spatial) {
     HIPCHK(&h, launch_force_spatial(h.nbl, a, h.sp, nsplit, s));
+  } else if (fused) {
+    HIPCHK(&h, launch_force_fused(h.prec, h.nbl, a, h.jm, h.ti, c.nbwork, status, nsplit, s));
   } else {
     HIPCHK(&h, launch_force(h.prec, h.nbl, a, nsplit, s));
   }
   if (ev) HIPCHK(&h, hipEventRecord(ev[2], s));
   HIPCHK(&h, launch_reduce(nsplit, ni, spatial ? h.sp.iperm : nullptr, a.part, a.nn_r2, a.nn_slot, h.jm.index,
-                           a.nb_count, a.nb_slot, h.nbl, d_acc, d_jerk, d_pot, d_nnb, d_r2nn, status,
-                           static_cast<int *>(h.d_ovf.p), s));
+                           a.nb_count, a.nb_slot, h.nbl, d_acc, d_jerk, d_pot, d_nnb, d_r2nn, status, c.ovf, s,
+                           c.nbwork));
+  // the reduction clears the fused counters again (without lists nothing was counted)
+  if (fused && !noalloc) h.nbwork_ok = true;
   if (ev) {
     HIPCHK(&h, hipEventRecord(ev[3], s));
     ++h.n_timed;
@@ -466,6 +595,10 @@ int enqueue_calc(Handle &h, int nj, int ni, const int *d_islot, const double *d_
   h.c_eps2 = eps2;
   h.c_stream = s;
   h.c_args = a;
+  h.c_fused = fused;
+  h.c_ti = h.ti;
+  h.c_flags = status;
+  h.c_ovf = c.ovf;
   h.c_prec = h.prec;
   h.c_nbl = h.nbl;
   h.c_have = true;
@@ -552,7 +685,7 @@ int firsthalf_impl(Handle &h, int nj, int ni, const int *index, const double (*x
                     reinterpret_cast<int *>(dout + ol.nnb),
                     reinterpret_cast<double *>(dout + ol.r2nn), s);
   if (rc) return rc;
-  HIPCHK(&h, hipMemcpyAsync(dout + ol.flags, h.d_flags.p, sizeof(int), hipMemcpyDeviceToDevice, s));
+  HIPCHK(&h, hipMemcpyAsync(dout + ol.flags, h.c_flags, sizeof(int), hipMemcpyDeviceToDevice, s));
   HIPCHK(&h, hipMemcpyAsync(h.h_out.p, h.d_out.p, ol.bytes, hipMemcpyDeviceToHost, s));
   h.c_index.assign(index, index + ni);
   return 0;
@@ -1055,14 +1188,17 @@ G6MI_API int g6_read_neighbour_list(int id) {
   if (n > 0 && h->c_nbl) {
     // overflowed lists: keep the G6MI_NB_MAX smallest indices (exact pass)
     int status[kStatusWords] = {0, 0};
-    HIPCHK(h, hipMemcpy(status, h->d_flags.p, sizeof(status), hipMemcpyDeviceToHost));
+    HIPCHK(h, hipMemcpy(status, h->c_batch ? h->c_bargs.status : h->c_flags, sizeof(status),
+                        hipMemcpyDeviceToHost));
     if (status[kStatusOverflowCount] > 0 && !h->nb_exact_done) {
       if (h->c_batch)
         HIPCHK(h, launch_batch_nb_exact(h->c_prec, h->c_bargs, status[kStatusOverflowCount], h->c_stream));
+      else if (h->c_fused)
+        HIPCHK(h, launch_nb_exact_fused(h->c_prec, h->c_args, h->jm, h->c_ti, h->c_flags, h->c_ovf,
+                                        status[kStatusOverflowCount], h->c_stream));
       else
-        HIPCHK(h, launch_nb_exact(h->c_prec, h->c_args, h->jm.index, static_cast<int *>(h->d_flags.p),
-                                  static_cast<int *>(h->d_ovf.p), status[kStatusOverflowCount],
-                                  h->c_stream));
+        HIPCHK(h, launch_nb_exact(h->c_prec, h->c_args, h->jm.index, h->c_flags, h->c_ovf,
+                                  status[kStatusOverflowCount], h->c_stream));
       HIPCHK(h, hipStreamSynchronize(h->c_stream));
       h->nb_exact_done = true;
     }
@@ -1070,9 +1206,9 @@ G6MI_API int g6_read_neighbour_list(int id) {
   h->r_nbcount.assign(n, 0);
   h->r_nblist.assign(n * kNbMax, -1);
   if (n > 0) {
-    HIPCHK(h, hipMemcpy(h->r_nbcount.data(), h->d_nbcount.p, n * sizeof(int), hipMemcpyDeviceToHost));
-    HIPCHK(h, hipMemcpy(h->r_nblist.data(), h->d_nblist.p, n * kNbMax * sizeof(int),
-                        hipMemcpyDeviceToHost));
+    const ForceArgs &ca = h->c_batch ? h->c_bargs.fa : h->c_args;
+    HIPCHK(h, hipMemcpy(h->r_nbcount.data(), ca.nb_count, n * sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(h, hipMemcpy(h->r_nblist.data(), ca.nb_slot, n * kNbMax * sizeof(int), hipMemcpyDeviceToHost));
   }
   h->nb_read = true;
   bool over = false;
@@ -1127,6 +1263,14 @@ G6MI_API int g6mi_set_spatial(int id, int mode) {
   if (!h) return code_for_missing(id);
   if (mode < 0 || mode > 2) return fail(h, G6MI_EINVAL, "spatial mode must be 0, 1 or 2");
   h->spatial = mode;
+  return G6MI_OK;
+}
+
+G6MI_API int g6mi_set_fused_predict(int id, int on) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  if (on != 0 && on != 1) return fail(h, G6MI_EINVAL, "fused prediction flag must be 0 or 1");
+  h->fuse = on != 0;
   return G6MI_OK;
 }
 
@@ -1280,7 +1424,7 @@ G6MI_API int g6mi_last_status(int id, int *flags) {
   HIPCHK(h, hipSetDevice(h->device));
   HIPCHK(h, hipStreamSynchronize(h->c_stream));
   int st[kStatusWords] = {0, 0};
-  HIPCHK(h, hipMemcpy(st, h->d_flags.p, sizeof(st), hipMemcpyDeviceToHost));
+  HIPCHK(h, hipMemcpy(st, h->c_batch ? h->c_bargs.status : h->c_flags, sizeof(st), hipMemcpyDeviceToHost));
   *flags = st[kStatusFlags];
   return G6MI_OK;
 }

@@ -31,24 +31,42 @@ template <int PREC> using real_t = std::conditional_t<PREC == G6MI_PREC_FP64, do
 
 // ---------------------------------------------------------------- predictor
 
+// The float64 j-memory entries of one slot that the predictor reads: a
+// kernel can load the next tile's entries into registers while it works on
+// the current one, and predict them later.
+struct JRaw {
+  double t, m, x[3], v[3], a2[3], j6[3];
+  __device__ __forceinline__ void load(const JMem &jm, size_t k) {
+    t = jm.t[k];
+    m = jm.m[k];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const size_t e = d * jm.cap + k;
+      x[d] = jm.x[e];
+      v[d] = jm.v[e];
+      a2[d] = jm.a2[e];
+      j6[d] = jm.j6[e];
+    }
+  }
+};
+
 // Sec. 2.2, Eq. (1) and (2), with the stored coefficients a2 = a/2 and
 // j6 = jerk/6 and tau = t_i - t_j, evaluated by Horner's rule in float64.
 // The double-single split (Sec. 2.2, Bailey's format) is hi = fl32(x),
-// lo = fl32(x - hi); x - hi is exact in float64.  Writes the record of slot
-// k in the layout of the precision variant to o (global memory or LDS).
+// lo = fl32(x - hi); x - hi is exact in float64.  Writes the record of the
+// slot held in r in the layout of the precision variant to o (global memory
+// or LDS).
 template <int PREC>
-__device__ __forceinline__ void predict_record(const JMem &jm, size_t k, double ti,
-                                               float4 *__restrict__ o) {
-  const double tau = ti - jm.t[k];
+__device__ __forceinline__ void predict_raw(const JRaw &r, double ti, float4 *__restrict__ o) {
+  const double tau = ti - r.t;
   double xp[3], vp[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const size_t e = d * jm.cap + k;
-    const double c2 = jm.a2[e], c3 = jm.j6[e], c1 = jm.v[e];
-    xp[d] = jm.x[e] + tau * (c1 + tau * (c2 + tau * c3));
+    const double c2 = r.a2[d], c3 = r.j6[d], c1 = r.v[d];
+    xp[d] = r.x[d] + tau * (c1 + tau * (c2 + tau * c3));
     vp[d] = c1 + tau * (2.0 * c2 + tau * (3.0 * c3));
   }
-  const double mk = jm.m[k];
+  const double mk = r.m;
   if constexpr (PREC == G6MI_PREC_DS) {
     float hi[3], lo[3];
 #pragma unroll
@@ -72,6 +90,15 @@ __device__ __forceinline__ void predict_record(const JMem &jm, size_t k, double 
     o2[2] = make_double2(vp[0], vp[1]);
     o2[3] = make_double2(vp[2], 0.0);
   }
+}
+
+// The record of slot k predicted to ti (predict_raw on its j-memory entries).
+template <int PREC>
+__device__ __forceinline__ void predict_record(const JMem &jm, size_t k, double ti,
+                                               float4 *__restrict__ o) {
+  JRaw r;
+  r.load(jm, k);
+  predict_raw<PREC>(r, ti, o);
 }
 
 // ------------------------------------------------------------- interaction
@@ -747,54 +774,69 @@ struct NarrowLane {
     resolve_group<PREC>(st, grp, L, src, base, ebest, eslot, slot);
   }
 
-  // Add the L lane totals of each i-particle through `red` (LDS, [9][kWG]
-  // doubles; the caller synchronises before reusing it) in a fixed binary
-  // tree: at each level lane `sub` < half adds lane sub + half.  Afterwards
-  // the lanes with sub == 0 hold the i-particle's totals in t and its
-  // nearest-neighbour candidate in (bestd, bslot).
+  // Add the L lane totals of each i-particle in a fixed order.  The lanes of
+  // i-particle il are tid = sub * ipw + il.  Within a wave (ipw < 64: 64 /
+  // ipw of them per wave) they meet in an xor butterfly of cross-lane
+  // exchanges over the lane bits from ipw up to 32; each exchange adds the
+  // same two operands on both lanes, so all of them end with the same bits.
+  // The P = 256 / max(ipw, 64) parts left (one per wave, or one per lane
+  // when ipw >= 64) go through `red` (LDS, [9][kWG] doubles; the caller
+  // synchronises before reusing it), and lane il adds parts 1 .. P - 1 in
+  // order.  Afterwards the lanes with sub == 0 (tid = il) hold the
+  // i-particle's totals in t and its nearest-neighbour candidate in
+  // (bestd, bslot).
   __device__ __forceinline__ void lane_sum(double *red, int tid, int il, int ipw, double &bestd,
                                            int &bslot) {
     bestd = static_cast<double>(ebest);
     bslot = eslot;
     if (L == 1) return;
+    for (int m = ipw; m < 64; m <<= 1) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        t.acc[d] += __shfl_xor(t.acc[d], m);
+        t.jrk[d] += __shfl_xor(t.jrk[d], m);
+      }
+      t.pot += __shfl_xor(t.pot, m);
+      const double r2o = __shfl_xor(bestd, m);
+      const int so = __shfl_xor(bslot, m);
+      nn_merge_lane(r2o, so, bestd, bslot);
+    }
+    const int stride = ipw < 64 ? 64 : ipw; // lanes between the holders of two parts
+    const int nparts = kWG / stride;
+    if (nparts == 1) return;
     int *rslot = reinterpret_cast<int *>(red + 8 * kWG);
     __syncthreads();
+    if (tid >= stride && (tid & (stride - 1)) == il) { // holder of part tid / stride > 0
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      red[d * kWG + tid] = t.acc[d];
-      red[(3 + d) * kWG + tid] = t.jrk[d];
+      for (int d = 0; d < 3; ++d) {
+        red[d * kWG + tid] = t.acc[d];
+        red[(3 + d) * kWG + tid] = t.jrk[d];
+      }
+      red[6 * kWG + tid] = t.pot;
+      red[7 * kWG + tid] = bestd;
+      rslot[tid] = bslot;
     }
-    red[6 * kWG + tid] = t.pot;
-    red[7 * kWG + tid] = bestd;
-    rslot[tid] = bslot;
-    for (int half = L >> 1; half > 0; half >>= 1) {
-      __syncthreads();
-      if (sub < half) {
-        const int o = (sub + half) * ipw + il;
+    __syncthreads();
+    if (tid == il) {
+      for (int p = 1; p < nparts; ++p) {
+        const int o = p * stride + il;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
           t.acc[d] += red[d * kWG + o];
           t.jrk[d] += red[(3 + d) * kWG + o];
         }
         t.pot += red[6 * kWG + o];
-        const double r2o = red[7 * kWG + o];
-        const int so = rslot[o];
-        if (so >= 0 && (r2o < bestd || (r2o == bestd && (bslot < 0 || so < bslot)))) {
-          bestd = r2o;
-          bslot = so;
-        }
+        nn_merge_lane(red[7 * kWG + o], rslot[o], bestd, bslot);
       }
-      __syncthreads();
-      if (sub < half) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          red[d * kWG + tid] = t.acc[d];
-          red[(3 + d) * kWG + tid] = t.jrk[d];
-        }
-        red[6 * kWG + tid] = t.pot;
-        red[7 * kWG + tid] = bestd;
-        rslot[tid] = bslot;
-      }
+    }
+  }
+
+  // (r2o, so) merged into (bestd, bslot): the lexicographic (r^2, slot)
+  // minimum over valid slots (order-independent).
+  __device__ __forceinline__ static void nn_merge_lane(double r2o, int so, double &bestd, int &bslot) {
+    if (so >= 0 && (r2o < bestd || (r2o == bestd && (bslot < 0 || so < bslot)))) {
+      bestd = r2o;
+      bslot = so;
     }
   }
 };
@@ -887,13 +929,17 @@ __device__ __forceinline__ void split_sum(int nsplit, int G, int g, int xs, cons
 // ovf_tag when given) for the exact pass, counted in
 // status[kStatusOverflowCount].  Returns the status flags of the row
 // (bit 0 non-finite output, bit 1 neighbour overflow).
+// nb_work: the interaction kernel counted the row's neighbours there instead
+// of in nb_count; the count is moved to nb_count and nb_work[row] cleared
+// for the next calculation (so that no launch has to clear it first).
 __device__ __forceinline__ int finish_out(const double s[7], double best, int bslot, int row,
                                           const int *__restrict__ jindex,
-                                          const int *__restrict__ nb_count, int *__restrict__ nb_slot,
+                                          int *__restrict__ nb_count, int *__restrict__ nb_slot,
                                           bool nbl, double *__restrict__ acc, double *__restrict__ jerk,
                                           double *__restrict__ pot, int *__restrict__ nnb,
                                           double *__restrict__ r2nn, int *__restrict__ status,
-                                          int *__restrict__ ovf_list, int *__restrict__ ovf_tag, int tag) {
+                                          int *__restrict__ ovf_list, int *__restrict__ ovf_tag, int tag,
+                                          int *__restrict__ nb_work = nullptr) {
   const size_t i = static_cast<size_t>(row);
   bool finite = true;
 #pragma unroll
@@ -907,8 +953,16 @@ __device__ __forceinline__ int finish_out(const double s[7], double best, int bs
   if (nnb) nnb[i] = bslot >= 0 ? jindex[bslot] : -1;
   if (r2nn) r2nn[i] = bslot >= 0 ? best : INFINITY;
   int fl = finite ? 0 : 1;
+  if (!nbl && nb_work) nb_count[i] = 0; // no list: no count left from an earlier call
   if (nbl) {
-    const int cnt = nb_count[i];
+    int cnt;
+    if (nb_work) {
+      cnt = nb_work[i];
+      nb_work[i] = 0;
+      nb_count[i] = cnt;
+    } else {
+      cnt = nb_count[i];
+    }
     int *lst = nb_slot + i * kNbMax;
     if (cnt > kNbMax) { // kept set decided later by the exact pass
       fl |= 2;

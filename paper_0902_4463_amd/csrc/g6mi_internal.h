@@ -24,6 +24,9 @@ namespace g6mi {
 #ifndef G6MI_FAR_K
 #define G6MI_FAR_K 1.0f // far tile: gap to the i-box at least this many tile radii
 #endif
+#ifndef G6MI_FUSED_DEPTH
+#define G6MI_FUSED_DEPTH 3 // records per lane in flight in the one-particle fused kernel
+#endif
 #ifndef G6MI_WIDE_WAVES
 #define G6MI_WIDE_WAVES 3 // register budget of the wide kernel: waves per SIMD (0: free)
 #endif
@@ -31,6 +34,7 @@ namespace g6mi {
 constexpr int kWG = 256;          // lanes per workgroup: four wave64
 constexpr int kTile = G6MI_TILE;  // j-records staged in LDS per tile
 constexpr int kNbMax = 256;       // neighbour slots per i-particle
+constexpr int kFusedDepth = G6MI_FUSED_DEPTH;
 
 // Status words of one calculation in device memory (zeroed by the predictor
 // launch): flags (bit 0 non-finite output, bit 1 neighbour overflow) and the
@@ -70,7 +74,7 @@ struct ForceArgs {
   double *part = nullptr;      // [nsplit][7][ni]: acc xyz, jerk xyz, sum m/r
   double *nn_r2 = nullptr;     // [nsplit][ni]
   int *nn_slot = nullptr;      // [nsplit][ni]
-  int *nb_count = nullptr;     // [ni]   (zeroed by the predictor launch)
+  int *nb_count = nullptr;     // [ni]   (zeroed by the predictor launch; see force_fused)
   int *nb_slot = nullptr;      // [ni][kNbMax]
 };
 
@@ -81,20 +85,37 @@ hipError_t launch_predict(int prec, int nj, double ti, const JMem &jm,
 hipError_t launch_force(int prec, bool nbl, const ForceArgs &a, int nsplit,
                         hipStream_t s);
 
+// One i-block of at most kWG i-particles (a.ipw <= kWG) with the predictor
+// fused into the tile load: reads the j-memory jm at time ti instead of
+// a.jpred, counts neighbours in nb_work (all zero before the launch; the
+// reduction with the same nb_work clears it again) and clears the status
+// words itself.
+hipError_t launch_force_fused(int prec, bool nbl, const ForceArgs &a, const JMem &jm, double ti,
+                              int *nb_work, int *status, int nsplit, hipStream_t s);
+
+// Clear n ints with a kernel (no memset node when captured in a graph).
+hipError_t launch_zero(int n, int *p, hipStream_t s);
+
 // iperm: row of the partials at each position (spatially ordered blocks),
-// or null where partials sit at their own rows.
+// or null where partials sit at their own rows.  nb_work: the counters of a
+// force_fused launch (moved to nb_count and cleared), or null.
 hipError_t launch_reduce(int nsplit, int ni, const int *iperm, const double *part,
                          const double *nn_r2, const int *nn_slot,
                          const int *jindex, int *nb_count, int *nb_slot,
                          bool nbl, double *acc, double *jerk, double *pot,
                          int *nnb, double *r2nn, int *status, int *ovf_list,
-                         hipStream_t s);
+                         hipStream_t s, int *nb_work = nullptr);
 
 // Rebuild the lists of the novf overflowed i-particles queued by the
 // reduction (see reduce_kernel) with the kNbMax smallest indices.
 hipError_t launch_nb_exact(int prec, const ForceArgs &a, const int *jindex,
                            const int *status, const int *ovf_list, int novf,
                            hipStream_t s);
+
+// The exact overflow pass after a force_fused launch (records predicted
+// again from jm at ti).
+hipError_t launch_nb_exact_fused(int prec, const ForceArgs &a, const JMem &jm, double ti,
+                                 const int *status, const int *ovf_list, int novf, hipStream_t s);
 
 // Scatter nd staged records into the j-memory.  rec is [nd][16] doubles:
 // t, m, x[3], v[3], a2[3], j6[3], index (as double), pad; slots is [nd].

@@ -178,8 +178,11 @@ __global__ __launch_bounds__(kWG) void force_kernel(ForceArgs a) {
     }
     __syncthreads();
     n.tile(tile, jbase, cnt, eps2, a.nb_count, a.nb_slot);
+    // while the tile is still in LDS: the exact nearest neighbour so far
+    // decides which groups of a ragged tile fold into float64 (fold_or_add),
+    // as in force_fused and the batched kernel
+    n.resolve(tile, jbase);
   }
-  n.resolve(jp, 0); // the group lies within one full tile, so its slots are < nj
 
   double bestd;
   int bslot;
@@ -198,6 +201,142 @@ __global__ __launch_bounds__(kWG) void force_kernel(ForceArgs a) {
   }
 }
 
+// ------------------------------------ small blocks, predictor fused in
+
+// A block of at most 256 i-particles (one i-block, NarrowLane as in
+// force_kernel) reads the float64 j-memory and predicts every tile into LDS
+// itself (Sec. 2.2 fused into the tile load, as in the batched kernel), so
+// the predicted records are never written to HBM and read back: for a block
+// of a few particles the step is the predictor's HBM traffic, 112 B per
+// j-particle instead of 112 + 48 + 48.  The next tile's j-memory entries are
+// loaded into registers while the current tile is evaluated.  The
+// neighbours are counted in nb_work, which the reduction clears again, so no
+// launch before this one has to clear counters; workgroup (0, 0) clears the
+// status words, which only the reduction after this launch writes.
+template <int PREC, bool NBL>
+__global__ __launch_bounds__(kWG) void force_fused(ForceArgs a, JMem jm, double ti, int *__restrict__ nb_work,
+                                                   int *__restrict__ status) {
+  constexpr int REC = rec4<PREC>();
+  __shared__ __attribute__((aligned(16))) unsigned char lds[narrow_lds_bytes<PREC>()];
+  float4 *tile = reinterpret_cast<float4 *>(lds);
+
+  const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && tid < kStatusWords) status[tid] = 0;
+  const int ipw = a.ipw;
+  const int il = tid & (ipw - 1);
+  const int i = blockIdx.x * ipw + il;
+  NarrowLane<PREC, NBL> n;
+  n.init(a, i, i < a.ni, tid >> a.log2ipw, 8 - a.log2ipw);
+  const real_t<PREC> eps2 = static_cast<real_t<PREC>>(a.eps2);
+
+  const int ntiles = (a.nj + kTile - 1) / kTile;
+  const int per = (ntiles + gridDim.y - 1) / gridDim.y;
+  const int tb = blockIdx.y * per;
+  const int te = min(ntiles, tb + per);
+
+  // lane tid predicts record tid of each tile; past nj it loads slot nj - 1
+  // (in bounds) and stores nothing
+  JRaw nxt;
+  if (tb < te) nxt.load(jm, static_cast<size_t>(min(tb * kTile + tid, a.nj - 1)));
+  for (int tt = tb; tt < te; ++tt) {
+    const int jbase = tt * kTile;
+    const int cnt = min(kTile, a.nj - jbase);
+    __syncthreads();
+    if (tid < cnt) predict_raw<PREC>(nxt, ti, tile + tid * REC);
+    if (tt + 1 < te) nxt.load(jm, static_cast<size_t>(min((tt + 1) * kTile + tid, a.nj - 1)));
+    __syncthreads();
+    n.tile(tile, jbase, cnt, eps2, nb_work, a.nb_slot);
+    n.resolve(tile, jbase); // while the tile is still in LDS
+  }
+
+  double bestd;
+  int bslot;
+  n.lane_sum(reinterpret_cast<double *>(lds), tid, il, ipw, bestd, bslot);
+  if (n.sub == 0 && n.valid) {
+    const size_t ni = static_cast<size_t>(a.ni);
+    double *p = a.part + static_cast<size_t>(blockIdx.y) * 7 * ni + i;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      p[d * ni] = n.t.acc[d];
+      p[(3 + d) * ni] = n.t.jrk[d];
+    }
+    p[6 * ni] = n.t.pot;
+    a.nn_r2[blockIdx.y * ni + i] = bestd;
+    a.nn_slot[blockIdx.y * ni + i] = bslot;
+  }
+}
+
+// One i-particle (ipw = 1, all 256 lanes on it): lane tid takes records
+// tid, tid + 256, ... of the split, predicts each one itself and uses it at
+// once, so no record goes through LDS and no barrier is needed; the next
+// record's j-memory entries are loaded while the current one is evaluated.
+// The arithmetic and the order of the sums are those of force_fused (and of
+// force_kernel on predicted records) for one i-particle: each record is a
+// group of one pair, added to the float64 totals.
+template <int PREC, bool NBL>
+__global__ __launch_bounds__(kWG) void force_fused_one(ForceArgs a, JMem jm, double ti, int *__restrict__ nb_work,
+                                                       int *__restrict__ status) {
+  constexpr int REC = rec4<PREC>();
+  __shared__ __attribute__((aligned(16))) double red[9 * kWG]; // lane_sum
+  const int tid = threadIdx.x;
+  if (blockIdx.y == 0 && tid < kStatusWords) status[tid] = 0;
+  NarrowLane<PREC, NBL> n;
+  n.init(a, 0, true, tid, 8);
+  const real_t<PREC> eps2 = static_cast<real_t<PREC>>(a.eps2);
+
+  const int ntiles = (a.nj + kTile - 1) / kTile;
+  const int per = (ntiles + gridDim.y - 1) / gridDim.y;
+  const int tb = blockIdx.y * per;
+  const int te = min(ntiles, tb + per);
+  const int je = min(a.nj, te * kTile);
+  // kFusedDepth records per lane in flight: record js + u * kWG sits in q[u]
+  // and is replaced, once used, by the one kFusedDepth records further on
+  constexpr int D = kFusedDepth;
+  JRaw q[D];
+  const int j0 = tb * kTile + tid;
+#pragma unroll
+  for (int u = 0; u < D; ++u)
+    if (j0 + u * kWG < je) q[u].load(jm, static_cast<size_t>(j0 + u * kWG));
+  for (int js = j0; js < je; js += D * kWG) {
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      const int jj = js + u * kWG;
+      if (jj < je) {
+        float4 rec[REC];
+        predict_raw<PREC>(q[u], ti, rec);
+        if (jj + D * kWG < je) q[u].load(jm, static_cast<size_t>(jj + D * kWG));
+        MaskedRun<PREC, NBL, false, true> run;
+        run.start();
+        run.step(n.st, n.ts, n.t, rec, jj, n.slot, eps2, n.h2, n.ebest, n.eslot, nb_work, a.nb_slot);
+        run.finish(n.ts);
+        fold(n.ts, n.t);
+      }
+    }
+  }
+
+  double bestd;
+  int bslot;
+  n.lane_sum(red, tid, 0, 1, bestd, bslot);
+  if (tid == 0) {
+    const size_t ni = static_cast<size_t>(a.ni);
+    double *p = a.part + static_cast<size_t>(blockIdx.y) * 7 * ni;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      p[d * ni] = n.t.acc[d];
+      p[(3 + d) * ni] = n.t.jrk[d];
+    }
+    p[6 * ni] = n.t.pot;
+    a.nn_r2[blockIdx.y * ni] = bestd;
+    a.nn_slot[blockIdx.y * ni] = bslot;
+  }
+}
+
+// Clear n counters (a new or regrown nb_work buffer).
+__global__ __launch_bounds__(256) void zero_kernel(int n, int *__restrict__ p) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k < n) p[k] = 0;
+}
+
 // --------------------------------------------------------------- reduction
 
 // 2^log2G lanes per i-particle (split_sum, then finish_out on the first
@@ -210,10 +349,11 @@ __global__ __launch_bounds__(kWG) void force_kernel(ForceArgs a) {
 __global__ __launch_bounds__(256) void reduce_kernel(
     int nsplit, int ni, int log2G, const int *__restrict__ iperm, const double *__restrict__ part,
     const double *__restrict__ nn_r2, const int *__restrict__ nn_slot,
-    const int *__restrict__ jindex, const int *__restrict__ nb_count,
+    const int *__restrict__ jindex, int *__restrict__ nb_count,
     int *__restrict__ nb_slot, int nbl, double *__restrict__ acc,
     double *__restrict__ jerk, double *__restrict__ pot, int *__restrict__ nnb,
-    double *__restrict__ r2nn, int *__restrict__ status, int *__restrict__ ovf_list) {
+    double *__restrict__ r2nn, int *__restrict__ status, int *__restrict__ ovf_list,
+    int *__restrict__ nb_work) {
   const long long t = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
   const int G = 1 << log2G;
   int ioff, g, xs;
@@ -227,7 +367,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(
   if (g != 0) return;
   const int row = iperm ? iperm[i] : static_cast<int>(i);
   const int fl = finish_out(sum, best, bslot, row, jindex, nb_count, nb_slot, nbl != 0, acc, jerk, pot, nnb, r2nn,
-                            status, ovf_list, nullptr, 0);
+                            status, ovf_list, nullptr, 0, nb_work);
   if (fl) atomicOr(status + kStatusFlags, fl);
 }
 
@@ -252,6 +392,31 @@ __global__ __launch_bounds__(kWG) void nb_exact_kernel(ForceArgs a, const int *_
     real_t<PREC> h2;
     load_i<PREC>(st, a, i, true, slot, h2);
     exact_list<PREC>(st, slot, h2, 0, a.nj, jindex, rec_of, a.nb_slot + static_cast<size_t>(i) * kNbMax,
+                     a.nb_count + i, s_cnt, s_keep);
+  }
+}
+
+// The same for a calculation of force_fused, which kept no predicted
+// records: each record is predicted again from the j-memory exactly as in
+// force_fused.
+template <int PREC>
+__global__ __launch_bounds__(kWG) void nb_exact_fused_kernel(ForceArgs a, JMem jm, double ti,
+                                                              const int *__restrict__ status,
+                                                              const int *__restrict__ ovf_list) {
+  __shared__ unsigned s_cnt;
+  __shared__ int s_keep[kNbMax];
+  auto rec_of = [jm, ti](int js, float4 *buf) -> const float4 * {
+    predict_record<PREC>(jm, static_cast<size_t>(js), ti, buf);
+    return buf;
+  };
+  const int novf = status[kStatusOverflowCount];
+  for (int q = blockIdx.x; q < novf; q += gridDim.x) {
+    const int i = ovf_list[q];
+    IState<PREC> st;
+    int slot;
+    real_t<PREC> h2;
+    load_i<PREC>(st, a, i, true, slot, h2);
+    exact_list<PREC>(st, slot, h2, 0, a.nj, jm.index, rec_of, a.nb_slot + static_cast<size_t>(i) * kNbMax,
                      a.nb_count + i, s_cnt, s_keep);
   }
 }
@@ -348,10 +513,44 @@ hipError_t launch_force(int prec, bool nbl, const ForceArgs &a, int nsplit, hipS
   return hipGetLastError();
 }
 
+template <int PREC>
+static void launch_fused_prec(bool nbl, const ForceArgs &a, const JMem &jm, double ti, int *nb_work, int *status,
+                              dim3 grid, hipStream_t s) {
+  if (a.ipw == 1) {
+    if (nbl)
+      hipLaunchKernelGGL((force_fused_one<PREC, true>), grid, dim3(kWG), 0, s, a, jm, ti, nb_work, status);
+    else
+      hipLaunchKernelGGL((force_fused_one<PREC, false>), grid, dim3(kWG), 0, s, a, jm, ti, nb_work, status);
+    return;
+  }
+  if (nbl)
+    hipLaunchKernelGGL((force_fused<PREC, true>), grid, dim3(kWG), 0, s, a, jm, ti, nb_work, status);
+  else
+    hipLaunchKernelGGL((force_fused<PREC, false>), grid, dim3(kWG), 0, s, a, jm, ti, nb_work, status);
+}
+
+hipError_t launch_force_fused(int prec, bool nbl, const ForceArgs &a, const JMem &jm, double ti, int *nb_work,
+                              int *status, int nsplit, hipStream_t s) {
+  if (a.ni <= 0 || a.ipw > kWG) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>((a.ni + a.ipw - 1) / a.ipw), static_cast<unsigned>(nsplit));
+  switch (prec) {
+  case G6MI_PREC_FP32: launch_fused_prec<G6MI_PREC_FP32>(nbl, a, jm, ti, nb_work, status, grid, s); break;
+  case G6MI_PREC_DS: launch_fused_prec<G6MI_PREC_DS>(nbl, a, jm, ti, nb_work, status, grid, s); break;
+  default: launch_fused_prec<G6MI_PREC_FP64>(nbl, a, jm, ti, nb_work, status, grid, s);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(int n, int *p, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(n)), dim3(256), 0, s, n, p);
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce(int nsplit, int ni, const int *iperm, const double *part, const double *nn_r2,
                          const int *nn_slot, const int *jindex, int *nb_count, int *nb_slot,
                          bool nbl, double *acc, double *jerk, double *pot, int *nnb,
-                         double *r2nn, int *status, int *ovf_list, hipStream_t s) {
+                         double *r2nn, int *status, int *ovf_list, hipStream_t s, int *nb_work) {
   if (ni <= 0) return hipSuccess;
   const int G = split_lanes(nsplit, ni);
   int log2G = 0;
@@ -360,7 +559,7 @@ hipError_t launch_reduce(int nsplit, int ni, const int *iperm, const double *par
   const long long lanes = waves * 64;
   hipLaunchKernelGGL(reduce_kernel, dim3(static_cast<unsigned>((lanes + 255) / 256)), dim3(256), 0, s, nsplit, ni,
                      log2G, iperm, part, nn_r2, nn_slot, jindex, nb_count, nb_slot, nbl ? 1 : 0, acc, jerk, pot,
-                     nnb, r2nn, status, ovf_list);
+                     nnb, r2nn, status, ovf_list, nb_work);
   return hipGetLastError();
 }
 
@@ -379,6 +578,23 @@ hipError_t launch_nb_exact(int prec, const ForceArgs &a, const int *jindex, cons
   case G6MI_PREC_FP32: launch_exact_prec<G6MI_PREC_FP32>(a, jindex, status, ovf_list, ngroups, s); break;
   case G6MI_PREC_DS: launch_exact_prec<G6MI_PREC_DS>(a, jindex, status, ovf_list, ngroups, s); break;
   default: launch_exact_prec<G6MI_PREC_FP64>(a, jindex, status, ovf_list, ngroups, s);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_nb_exact_fused(int prec, const ForceArgs &a, const JMem &jm, double ti, const int *status,
+                                 const int *ovf_list, int novf, hipStream_t s) {
+  if (novf <= 0) return hipSuccess;
+  const dim3 grid(static_cast<unsigned>(novf < 1024 ? novf : 1024));
+  switch (prec) {
+  case G6MI_PREC_FP32:
+    hipLaunchKernelGGL(nb_exact_fused_kernel<G6MI_PREC_FP32>, grid, dim3(kWG), 0, s, a, jm, ti, status, ovf_list);
+    break;
+  case G6MI_PREC_DS:
+    hipLaunchKernelGGL(nb_exact_fused_kernel<G6MI_PREC_DS>, grid, dim3(kWG), 0, s, a, jm, ti, status, ovf_list);
+    break;
+  default:
+    hipLaunchKernelGGL(nb_exact_fused_kernel<G6MI_PREC_FP64>, grid, dim3(kWG), 0, s, a, jm, ti, status, ovf_list);
   }
   return hipGetLastError();
 }

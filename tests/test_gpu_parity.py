@@ -251,6 +251,62 @@ def test_neighbour_overflow_shuffled_indices(g6, orc, sess, prec):
     assert nb["ok"], nb
 
 
+# ------------------------------------------- predictor fused into small blocks
+
+FUSED_CASES = [(1, 1), (4097, 1), (4097, 7), (5000, 256), (700, 100), (300, 256)]
+
+
+@pytest.mark.parametrize("n,ni", FUSED_CASES)
+@pytest.mark.parametrize("prec", ["ds", "fp64", "fp32"])
+def test_fused_prediction_matches_separate_predictor(g6, orc, sess, n, ni, prec):
+    """Blocks of at most 256 i-particles predict their j-tiles inside the
+    interaction kernel, with the arithmetic of the separate predictor: the
+    results agree with that path bit for bit and meet the oracle's
+    tolerances (float32 reported, not graded)."""
+    jm = workloads.random_cluster(n, seed=3000 + n)
+    slots = workloads.active_set(n, ni, seed=ni)
+    eps2, h2 = 1e-4, 0.05
+    ref = with_xp(orc, jm, oracle_eval(orc, jm, slots, eps2, h2))
+    sess.load(jm)
+    fused = gpu_eval(sess, g6, jm, slots, ref, eps2, h2, prec)
+    g6.check(sess.id, g6.g6mi_set_fused_predict(sess.id, 0))
+    try:
+        sep = gpu_eval(sess, g6, jm, slots, ref, eps2, h2, prec)
+    finally:
+        g6.check(sess.id, g6.g6mi_set_fused_predict(sess.id, 1))
+    for key in ("acc", "jerk", "pot", "nn_index", "nn_r2", "nb_count", "nb_list"):
+        assert np.array_equal(fused[key], sep[key]), key
+    assert_parity(fused, ref, jm, h2, prec, f"fused N={n} ni={ni}", strict=prec != "fp32")
+
+
+@pytest.mark.parametrize("prec", ["ds", "fp64"])
+def test_fused_neighbour_overflow_and_fresh_counters(g6, orc, sess, prec):
+    """Fused small blocks in a row on one handle: lists that all overflow
+    (the exact pass predicts the records again from the j-memory), a call
+    with lists near their radius, and again overflowing lists: each call
+    starts from cleared counters, which no launch clears beforehand (the
+    reduction of the previous call does)."""
+    rng = np.random.default_rng(63)
+    n = 3000
+    x = rng.normal(size=(n, 3)) * 0.01
+    idx = (rng.permutation(n) * 3 + 5).astype(np.int32)
+    jm = workloads.make_jmemory(x, rng.normal(size=(n, 3)), np.full(n, 1 / n), index=idx, meta=dict(ti=0.0))
+    sess.load(jm)
+    xp, _ = orc.predict(0.0, jm.t, jm.x, jm.v, jm.a2, jm.j6)
+    for ni, h2 in ((200, 1.0), (37, 1e-5), (5, 1.0), (200, 1e-5)):
+        slots = workloads.active_set(n, ni, seed=ni)
+        ref = oracle_eval(orc, jm, slots, 1e-6, h2)
+        gpu = gpu_eval(sess, g6, jm, slots, ref, 1e-6, h2, prec)
+        if h2 == 1.0:
+            assert gpu["nb_overflow"] and (ref["nb_count"] > 256).all()
+            assert np.array_equal(gpu["nb_count"], ref["nb_count"])
+            assert np.array_equal(gpu["nb_list"], ref["nb_list"])
+        else:
+            nb = parity.nb_report(gpu["nb_count"], gpu["nb_list"], ref["nb_count"], ref["nb_list"], xp, jm.index,
+                                  ref["xi"], h2)
+            assert nb["ok"] and nb["overflow_rows"] == 0, nb
+
+
 def test_nonfinite_output_is_flagged(g6, sess):
     """eps = 0 with two distinct particles at the same place: the result is
     not finite and lasthalf says so with return code 1."""
