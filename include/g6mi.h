@@ -304,6 +304,33 @@ int g6mi_calc_device(int id, int nj, int ni, const int *d_islot,
                      const double *d_h2, double *d_acc, double *d_jerk,
                      double *d_pot, int *d_nnb, double *d_r2nn, void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, hosts that forbid allocation during a run):
+ * g6mi_calc_device_noalloc is g6mi_calc_device with every work buffer of the
+ * calculation (predicted records, split partials, neighbour counters and
+ * slots, status words, overflow queue) cut from one static device array of
+ * G6MI_NOALLOC_SCRATCH_BYTES per GPU instead of the handle's memory.  It
+ * calls no hipMalloc, hipFree or other allocating routine; the caller
+ * passes inputs and outputs as for g6mi_calc_device, and the j-memory must
+ * already hold slots 0..nj-1 on the device (g6mi_set_j_particles_device, or
+ * an earlier calculation after g6_set_j_particle).  Differences: the
+ * calculation is never spatially ordered, it is not timed, and its j-split
+ * count is lowered until the buffers fit.  Returns 0, G6MI_EINVAL (also
+ * when the work buffers do not fit even with one j-split: roughly
+ * 48 B x nj (DS; 32 B FP32, 64 B FP64; none for a single block of at most
+ * 256 i-particles) plus about 1.1 KB x ni), G6MI_ESTATE (j-particles set on
+ * the host not uploaded yet, or fewer than nj slots on the device) or
+ * G6MI_EDEVICE.  Every call on one GPU shares that GPU's array, which keeps
+ * the last call's contents: the neighbour lists read afterwards with
+ * g6_read_neighbour_list are those of the last call on that GPU, and calls
+ * on one GPU that overlap in time (other streams, other threads or handles)
+ * race on it. */
+#define G6MI_NOALLOC_SCRATCH_BYTES (64u << 20)
+int g6mi_calc_device_noalloc(int id, int nj, int ni, const int *d_islot,
+                             const double *d_xi, const double *d_vi, double eps2,
+                             const double *d_h2, double *d_acc, double *d_jerk,
+                             double *d_pot, int *d_nnb, double *d_r2nn, void *stream);
+
 /* Device properties used by the launch heuristics: compute units and peak
  * engine clock in MHz.  Returns 0 or a negative code. */
 int g6mi_device_info(int id, int info[2]);

@@ -82,6 +82,7 @@ _SIGS = {
     "g6mi_timing_totals": (_i, [_i, _D, _I]),
     "g6mi_set_j_particles_device": (_i, [_i, _i, _V, _V, _V, _V, _V, _V, _V, _V]),
     "g6mi_calc_device": (_i, [_i, _i, _i, _V, _V, _V, _d, _V, _V, _V, _V, _V, _V, _V]),
+    "g6mi_calc_device_noalloc": (_i, [_i, _i, _i, _V, _V, _V, _d, _V, _V, _V, _V, _V, _V, _V]),
     "g6mi_device_info": (_i, [_i, _I]),
     "g6mi_last_status": (_i, [_i, _I]),
     "g6mi_batch_calc": (_i, [_i, _i, _V, _i, _V, _V, _V, _V, _V, _V, _V, _V, _V, _V]),
@@ -326,6 +327,15 @@ def g6mi_calc_device(id, nj, ni, islot, xi, vi, eps2, h2, acc, jerk, pot, nnb=No
     return _L().g6mi_calc_device(id, int(nj), int(ni), _ptr(islot), _ptr(xi), _ptr(vi),
                                  float(eps2), _ptr(h2), _ptr(acc), _ptr(jerk), _ptr(pot),
                                  _ptr(nnb), _ptr(r2nn), _stream(stream))
+
+
+def g6mi_calc_device_noalloc(id, nj, ni, islot, xi, vi, eps2, h2, acc, jerk, pot, nnb=None, r2nn=None,
+                             stream=None) -> int:
+    """g6mi_calc_device with its work buffers in the library's static
+    per-GPU scratch array (no allocation)."""
+    return _L().g6mi_calc_device_noalloc(id, int(nj), int(ni), _ptr(islot), _ptr(xi), _ptr(vi),
+                                         float(eps2), _ptr(h2), _ptr(acc), _ptr(jerk), _ptr(pot),
+                                         _ptr(nnb), _ptr(r2nn), _stream(stream))
 
 
 def g6mi_device_info(id):

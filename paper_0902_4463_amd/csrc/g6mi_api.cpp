@@ -1266,6 +1266,31 @@ G6MI_API int g6mi_set_spatial(int id, int mode) {
   return G6MI_OK;
 }
 
+G6MI_API int g6mi_calc_device_noalloc(int id, int nj, int ni, const int *d_islot, const double *d_xi,
+                                      const double *d_vi, double eps2, const double *d_h2,
+                                      double *d_acc, double *d_jerk, double *d_pot, int *d_nnb,
+                                      double *d_r2nn, void *stream) {
+  Handle *h = get_open(id);
+  if (!h) return code_for_missing(id);
+  if (h->pending) return fail(h, G6MI_ESTATE, "a host-path calculation is pending");
+  if (nj < 0 || static_cast<size_t>(nj) > h->n_contig)
+    return fail(h, G6MI_EINVAL, "nj exceeds the number of j-slots set from slot 0");
+  if (ni < 0 || ni > G6MI_NI_MAX) return fail(h, G6MI_EINVAL, "ni out of range");
+  if (ni > 0 && (!d_islot || !d_xi || !d_vi || !d_h2 || !d_acc || !d_jerk || !d_pot))
+    return fail(h, G6MI_EINVAL, "null device array");
+  if (!std::isfinite(eps2) || eps2 < 0.0) return fail(h, G6MI_EINVAL, "eps2 must be finite and >= 0");
+  if (!h->jm.t || static_cast<size_t>(std::max(nj, 1)) > h->jm.cap)
+    return fail(h, G6MI_ESTATE, "the device j-memory holds fewer than nj slots");
+  HIPCHK(h, hipSetDevice(h->device));
+  void *scr = nullptr;
+  size_t scr_bytes = 0;
+  HIPCHK(h, scratch_region(h->device, &scr, &scr_bytes));
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : h->stream;
+  h->res_valid = false;
+  return enqueue_calc(*h, nj, ni, d_islot, d_xi, d_vi, d_h2, eps2, d_acc, d_jerk, d_pot, d_nnb, d_r2nn, s,
+                      scr, scr_bytes);
+}
+
 G6MI_API int g6mi_set_fused_predict(int id, int on) {
   Handle *h = get_open(id);
   if (!h) return code_for_missing(id);

@@ -93,6 +93,11 @@ hipError_t launch_force(int prec, bool nbl, const ForceArgs &a, int nsplit,
 hipError_t launch_force_fused(int prec, bool nbl, const ForceArgs &a, const JMem &jm, double ti,
                               int *nb_work, int *status, int nsplit, hipStream_t s);
 
+// Device address and size of the calling thread's current device's static
+// scratch array (g6mi_calc_device_noalloc); `device` must be current.  The
+// address is looked up once per device and kept.
+hipError_t scratch_region(int device, void **ptr, size_t *bytes);
+
 // Clear n ints with a kernel (no memset node when captured in a graph).
 hipError_t launch_zero(int n, int *p, hipStream_t s);
 

@@ -16,6 +16,8 @@
 
 #include "g6mi_device.h"
 
+#include <mutex>
+
 namespace g6mi {
 
 size_t pred_record_bytes(int prec) {
@@ -461,6 +463,38 @@ __global__ __launch_bounds__(256) void load_kernel(int nj, const double *__restr
     jm.a2[d * jm.cap + k] = a2[3 * static_cast<size_t>(k) + d];
     jm.j6[d * jm.cap + k] = j6[3 * static_cast<size_t>(k) + d];
   }
+}
+
+// ------------------------------------------------------ static scratch
+
+// Work buffers of g6mi_calc_device_noalloc (callers that cannot allocate):
+// one array of G6MI_NOALLOC_SCRATCH_BYTES in each GPU's memory, held from
+// the library's load on that GPU until the process ends.  In host code the
+// name stands for no device address: only the address that
+// hipGetSymbolAddress returns for the current device is used.
+static __device__ __align__(256) unsigned char scratch[G6MI_NOALLOC_SCRATCH_BYTES];
+
+hipError_t scratch_region(int device, void **ptr, size_t *bytes) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void *addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    // once per device, with that device current
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  *bytes = sizeof(scratch);
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------- launchers
