@@ -271,12 +271,17 @@ __device__ __forceinline__ real_t<PREC> pair_core(const IState<PREC> &st, Sums<r
   using R = real_t<PREC>;
   R d[3], w[3], mj;
   separation<PREC>(st, rec, d, w, mj);
-  const R r2u = sq3<PREC>(d);
+  R r2u = sq3<PREC>(d);
+  constexpr bool kInfSelf = SELF && PREC != G6MI_PREC_FP64 && G6MI_SELF_INF;
+  // float32: the self pair's r^2 becomes +inf before the softening, and the
+  // hardware's 1/sqrt(+inf) is +0, so one select serves both uses (float64's
+  // Newton steps would turn +inf * 0 into NaN, so it selects rinv instead)
+  if constexpr (kInfSelf) r2u = self ? R(INFINITY) : r2u;
   const R s = r2u + eps2;
   R rinv;
   if constexpr (PREC == G6MI_PREC_FP64) rinv = rsqrt_f64(s);
   else rinv = __builtin_amdgcn_rsqf(s);
-  if constexpr (SELF) rinv = self ? R(0) : rinv;
+  if constexpr (SELF && !kInfSelf) rinv = self ? R(0) : rinv;
   const R rinv2 = rinv * rinv;
   const R mr = mj * rinv;
   const R mr3 = mr * rinv2;
@@ -299,7 +304,7 @@ __device__ __forceinline__ real_t<PREC> pair_core(const IState<PREC> &st, Sums<r
       acc.j2[k] += mr3t * d[k];
     }
   }
-  if constexpr (SELF) return self ? R(INFINITY) : r2u;
+  if constexpr (SELF && !kInfSelf) return self ? R(INFINITY) : r2u;
   else return r2u;
 }
 
@@ -750,7 +755,8 @@ struct NarrowLane {
           const int jj = sub + ((k0 + u) << log2L);
           m = fmin(m, pair_core<PREC, false, SELF>(st, gs, tl + jj * REC, eps2, jj == o));
         }
-        fold_or_add(gs, ts, t, m < gbest);
+        if constexpr (G6MI_NARROW_FOLD) fold(gs, t);
+        else fold_or_add(gs, ts, t, m < gbest);
       }
       if (m < gbest) {
         gbest = m;

@@ -27,6 +27,12 @@ namespace g6mi {
 #ifndef G6MI_FUSED_DEPTH
 #define G6MI_FUSED_DEPTH 3 // records per lane in flight in the one-particle fused kernel
 #endif
+#ifndef G6MI_SELF_INF
+#define G6MI_SELF_INF 1 // float32 self pair excluded through r^2 = +inf (one select)
+#endif
+#ifndef G6MI_NARROW_FOLD
+#define G6MI_NARROW_FOLD 0 // narrow blocks: every group sum straight into float64
+#endif
 #ifndef G6MI_WIDE_WAVES
 #define G6MI_WIDE_WAVES 3 // register budget of the wide kernel: waves per SIMD (0: free)
 #endif
