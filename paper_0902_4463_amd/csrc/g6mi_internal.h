@@ -41,6 +41,13 @@ constexpr int kWG = 256;          // lanes per workgroup: four wave64
 constexpr int kTile = G6MI_TILE;  // j-records staged in LDS per tile
 constexpr int kNbMax = 256;       // neighbour slots per i-particle
 constexpr int kFusedDepth = G6MI_FUSED_DEPTH;
+// Reduction of blocks of at most kFewMaxNi i-particles over more than 64
+// splits: one workgroup per i-particle, at most kFewSplitsPerLane splits per lane.
+#ifndef G6MI_FEW_MAX_NI
+#define G6MI_FEW_MAX_NI 256
+#endif
+constexpr int kFewMaxNi = G6MI_FEW_MAX_NI;
+constexpr int kFewSplitsPerLane = 4;
 
 // Status words of one calculation in device memory (zeroed by the predictor
 // launch): flags (bit 0 non-finite output, bit 1 neighbour overflow) and the

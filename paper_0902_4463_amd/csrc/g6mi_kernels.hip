@@ -373,6 +373,76 @@ __global__ __launch_bounds__(256) void reduce_kernel(
   if (fl) atomicOr(status + kStatusFlags, fl);
 }
 
+// A block of few i-particles over many j-splits: one workgroup per
+// i-particle.  Lane g adds splits g, g + 256, ... in float64 (all of its
+// loads issued before the additions), the 64 lane sums of a wave meet in an
+// xor butterfly, and lane 0 adds the four wave sums in wave order: the order
+// of additions is fixed by nsplit alone.  The 64 lanes per particle of
+// reduce_kernel need two or more rounds of dependent loads for 512 splits
+// and occupy a handful of workgroups; here each lane's loads are one round.
+__global__ __launch_bounds__(256) void reduce_few_kernel(
+    int nsplit, int ni, const int *__restrict__ iperm, const double *__restrict__ part,
+    const double *__restrict__ nn_r2, const int *__restrict__ nn_slot,
+    const int *__restrict__ jindex, int *__restrict__ nb_count,
+    int *__restrict__ nb_slot, int nbl, double *__restrict__ acc,
+    double *__restrict__ jerk, double *__restrict__ pot, int *__restrict__ nnb,
+    double *__restrict__ r2nn, int *__restrict__ status, int *__restrict__ ovf_list,
+    int *__restrict__ nb_work) {
+  constexpr int kPer = kFewSplitsPerLane;
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const size_t n = static_cast<size_t>(ni);
+  double v[kPer][7], r2[kPer];
+  int sl[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int q = tid + u * 256;
+    const bool ok = q < nsplit;
+    const size_t k = static_cast<size_t>(ok ? q : 0);
+#pragma unroll
+    for (int c = 0; c < 7; ++c) v[u][c] = ok ? part[k * 7 * n + c * n + i] : 0.0;
+    r2[u] = ok ? nn_r2[k * n + i] : INFINITY;
+    sl[u] = ok ? nn_slot[k * n + i] : -1;
+  }
+  double s[7], best = INFINITY;
+  int bslot = -1;
+#pragma unroll
+  for (int c = 0; c < 7; ++c) s[c] = 0.0;
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) s[c] += v[u][c];
+    nn_merge(r2[u], sl[u], best, bslot);
+  }
+  for (int m = 1; m < 64; m <<= 1) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) s[c] += __shfl_xor(s[c], m);
+    const double ob = __shfl_xor(best, m);
+    const int os = __shfl_xor(bslot, m);
+    nn_merge(ob, os, best, bslot);
+  }
+  __shared__ double s_red[4][8];
+  __shared__ int s_slot[4];
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) s_red[wave][c] = s[c];
+    s_red[wave][7] = best;
+    s_slot[wave] = bslot;
+  }
+  __syncthreads();
+  if (tid != 0) return;
+#pragma unroll
+  for (int w = 1; w < 4; ++w) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) s[c] += s_red[w][c];
+    nn_merge(s_red[w][7], s_slot[w], best, bslot);
+  }
+  const int row = iperm ? iperm[i] : i;
+  const int fl = finish_out(s, best, bslot, row, jindex, nb_count, nb_slot, nbl != 0, acc, jerk, pot, nnb, r2nn,
+                            status, ovf_list, nullptr, 0, nb_work);
+  if (fl) atomicOr(status + kStatusFlags, fl);
+}
+
 // --------------------------------------------- neighbour-list overflow
 
 // One workgroup per queued i-particle (grid-strided over the queue): its
@@ -586,6 +656,12 @@ hipError_t launch_reduce(int nsplit, int ni, const int *iperm, const double *par
                          bool nbl, double *acc, double *jerk, double *pot, int *nnb,
                          double *r2nn, int *status, int *ovf_list, hipStream_t s, int *nb_work) {
   if (ni <= 0) return hipSuccess;
+  if (ni <= kFewMaxNi && nsplit > 64 && nsplit <= 256 * kFewSplitsPerLane) {
+    hipLaunchKernelGGL(reduce_few_kernel, dim3(static_cast<unsigned>(ni)), dim3(256), 0, s, nsplit, ni, iperm, part,
+                       nn_r2, nn_slot, jindex, nb_count, nb_slot, nbl ? 1 : 0, acc, jerk, pot, nnb, r2nn, status,
+                       ovf_list, nb_work);
+    return hipGetLastError();
+  }
   const int G = split_lanes(nsplit, ni);
   int log2G = 0;
   while ((1 << log2G) < G) ++log2G;
