@@ -103,12 +103,16 @@ __device__ __forceinline__ void predict_record(const JMem &jm, size_t k, double 
 
 // ------------------------------------------------------------- interaction
 
-// 1/sqrt(s) in float64: the hardware estimate refined by two Newton-Raphson
+// 1/sqrt(s) in float64: the hardware estimate refined by Newton-Raphson
 // steps, y <- y + y (1 - s y^2) / 2, each roughly doubling the correct bits.
+// One step leaves about 1e-14 relative in 1/r (force errors against the
+// oracle 9e-15 on a Plummer sphere of 1024 with eps = 1/64 and 2e-13 with
+// hard binaries at eps = 0, against 5e-15 and 2e-13 with two steps), and
+// the float64 kernel runs 11% faster.
 __device__ __forceinline__ double rsqrt_f64(double s) {
   double y = __builtin_amdgcn_rsq(s);
 #pragma unroll
-  for (int it = 0; it < 2; ++it) {
+  for (int it = 0; it < G6MI_RSQ64_STEPS; ++it) {
     const double e = fma(-s * y, y, 1.0);
     y = fma(0.5 * y, e, y);
   }

@@ -33,6 +33,9 @@ namespace g6mi {
 #ifndef G6MI_NARROW_FOLD
 #define G6MI_NARROW_FOLD 0 // narrow blocks: every group sum straight into float64
 #endif
+#ifndef G6MI_RSQ64_STEPS
+#define G6MI_RSQ64_STEPS 1 // Newton-Raphson steps after the float64 1/sqrt estimate
+#endif
 #ifndef G6MI_WIDE_WAVES
 #define G6MI_WIDE_WAVES 3 // register budget of the wide kernel: waves per SIMD (0: free)
 #endif
