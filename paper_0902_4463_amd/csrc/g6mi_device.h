@@ -18,6 +18,12 @@ namespace g6mi {
 // j-records per group: the unit of the nearest-neighbour bookkeeping, of the
 // neighbour-list flags and of the first level of float32 summation.
 constexpr int kGroup = G6MI_GROUP;
+// Group length of the spatially ordered kernel (force_spatial).  Nine tiles
+// in ten are far there, their pair terms within a small factor of each
+// other, and the near tiles fold every group into float64; a longer group
+// spreads the per-group work (nearest-neighbour and neighbour tests, the
+// add into the tile sums) over more pairs.
+constexpr int kSpatialGroup = G6MI_SPATIAL_GROUP;
 static_assert(kTile / kGroup <= 32, "one mask bit per group");
 static_assert(kTile % kGroup == 0, "whole groups per tile");
 static_assert(kTile == kWG, "one j-record per lane when a tile is predicted in place");
@@ -423,18 +429,18 @@ __device__ __forceinline__ void nb_append(int *__restrict__ nb_count, int *__res
 // float4's w component; the first three floats are DS lo or velocity).
 __device__ __forceinline__ int rec_slot(const float4 *rec) { return __float_as_int(rec[1].w); }
 
-// Exact slot of a grouped-path nearest neighbour: re-examine the kGroup
-// records of the group starting at position grp (positions grp, grp +
+// Exact slot of a grouped-path nearest neighbour: re-examine the G records
+// of the group starting at position grp (positions grp, grp +
 // stride, ...) and merge the lexicographic (r^2, slot) minimum into (best,
 // bslot).  The record at position js is at src + (js - base) records; its
 // slot is js, or (SORTED) the slot stored in the record.  Clears grp.
-template <int PREC, bool SORTED = false>
+template <int PREC, bool SORTED = false, int G = kGroup>
 __device__ __forceinline__ void resolve_group(const IState<PREC> &st, int &grp, int stride,
                                               const float4 *__restrict__ src, int base,
                                               real_t<PREC> &best, int &bslot, int islot = -1) {
   constexpr int REC = rec4<PREC>();
   if (grp < 0) return;
-  for (int u = 0; u < kGroup; ++u) {
+  for (int u = 0; u < G; ++u) {
     const int js = grp + u * stride;
     const float4 *rec = src + static_cast<size_t>(js - base) * REC;
     const real_t<PREC> r = r2_of<PREC>(st, rec);
@@ -469,8 +475,9 @@ __device__ __forceinline__ void resolve_group(const IState<PREC> &st, int &grp, 
 // caller), and the slots of neighbours and nearest neighbours are read from
 // the records.  tile_far walks a far tile in float32 coordinates relative to
 // the tile's centre (see force_spatial).
-template <int PREC, bool NBL, bool SORTED = false>
+template <int PREC, bool NBL, bool SORTED = false, int G = kGroup>
 struct WideLanes {
+  static_assert(kTile % G == 0 && kTile / G <= 32, "whole groups per tile, one mask bit each");
   using R = real_t<PREC>;
   static constexpr int REC = rec4<PREC>();
   IState<PREC> s0, s1;
@@ -560,11 +567,11 @@ struct WideLanes {
     // bit k of nbm0 / nbm1: group k holds a neighbour of i0 / i1
     unsigned nbm0 = 0u, nbm1 = 0u;
 #pragma unroll G6MI_GROUP_UNROLL
-    for (int g = 0; g < kTile; g += kGroup) {
+    for (int g = 0; g < kTile; g += G) {
       R m0 = R(INFINITY), m1 = R(INFINITY);
       if constexpr (PREC == G6MI_PREC_FP64) {
 #pragma unroll
-        for (int u = 0; u < kGroup; ++u) {
+        for (int u = 0; u < G; ++u) {
           const float4 *rec = tl + (g + u) * REC;
           m0 = fmin(m0, pair_core<PREC, false, SELF>(s0, ts0, rec, eps2, g + u == o0));
           m1 = fmin(m1, pair_core<PREC, false, SELF>(s1, ts1, rec, eps2, g + u == o1));
@@ -574,7 +581,7 @@ struct WideLanes {
         m0 = pair_core<PREC, true, SELF>(s0, g0, tl + g * REC, eps2, g == o0);
         m1 = pair_core<PREC, true, SELF>(s1, g1, tl + g * REC, eps2, g == o1);
 #pragma unroll
-        for (int u = 1; u < kGroup; ++u) {
+        for (int u = 1; u < G; ++u) {
           const float4 *rec = tl + (g + u) * REC;
           m0 = fmin(m0, pair_core<PREC, false, SELF>(s0, g0, rec, eps2, g + u == o0));
           m1 = fmin(m1, pair_core<PREC, false, SELF>(s1, g1, rec, eps2, g + u == o1));
@@ -597,8 +604,8 @@ struct WideLanes {
       }
       if constexpr (NBL) {
         // the group minimum also tells whether any record is a neighbour
-        nbm0 |= (m0 < h20 ? 1u : 0u) << (g / kGroup);
-        nbm1 |= (m1 < h21 ? 1u : 0u) << (g / kGroup);
+        nbm0 |= (m0 < h20 ? 1u : 0u) << (g / G);
+        nbm1 |= (m1 < h21 ? 1u : 0u) << (g / G);
       }
     }
     if constexpr (NBL) {
@@ -606,8 +613,8 @@ struct WideLanes {
       while (nbm0 | nbm1) {
         const int k = __builtin_ctz(nbm0 | nbm1);
         const unsigned bit = 1u << k;
-        for (int u = 0; u < kGroup; ++u) {
-          const int jj = k * kGroup + u;
+        for (int u = 0; u < G; ++u) {
+          const int jj = k * G + u;
           const float4 *rec = tl + jj * REC;
           if ((nbm0 & bit) && (!SELF || jj != o0) && r2_of<PREC>(s0, rec) < h20)
             nb_append(nb_count, nb_slot, row0, jslot_at(tl, jbase, jj));
@@ -622,8 +629,8 @@ struct WideLanes {
 
   // Resolve the pending groups from records at src (position js at js - base).
   __device__ __forceinline__ void resolve(const float4 *__restrict__ src, int base) {
-    resolve_group<PREC, SORTED>(s0, grp0, 1, src, base, ebest0, eslot0, slot0);
-    resolve_group<PREC, SORTED>(s1, grp1, 1, src, base, ebest1, eslot1, slot1);
+    resolve_group<PREC, SORTED, G>(s0, grp0, 1, src, base, ebest0, eslot0, slot0);
+    resolve_group<PREC, SORTED, G>(s1, grp1, 1, src, base, ebest1, eslot1, slot1);
   }
 
   // A full far tile in float32 records relative to the tile's centre
@@ -638,12 +645,12 @@ struct WideLanes {
     constexpr int FREC = rec4<G6MI_PREC_FP32>();
     unsigned nbm0 = 0u, nbm1 = 0u;
 #pragma unroll G6MI_GROUP_UNROLL
-    for (int g = 0; g < kTile; g += kGroup) {
+    for (int g = 0; g < kTile; g += G) {
       Sums<R> g0, g1;
       R m0 = pair_core<G6MI_PREC_FP32, true>(f0, g0, ftl + g * FREC, eps2);
       R m1 = pair_core<G6MI_PREC_FP32, true>(f1, g1, ftl + g * FREC, eps2);
 #pragma unroll
-      for (int u = 1; u < kGroup; ++u) {
+      for (int u = 1; u < G; ++u) {
         const float4 *rec = ftl + (g + u) * FREC;
         m0 = fmin(m0, pair_core<G6MI_PREC_FP32>(f0, g0, rec, eps2));
         m1 = fmin(m1, pair_core<G6MI_PREC_FP32>(f1, g1, rec, eps2));
@@ -659,16 +666,16 @@ struct WideLanes {
         grp1 = jbase + g;
       }
       if constexpr (NBL) {
-        nbm0 |= (m0 < h20 ? 1u : 0u) << (g / kGroup);
-        nbm1 |= (m1 < h21 ? 1u : 0u) << (g / kGroup);
+        nbm0 |= (m0 < h20 ? 1u : 0u) << (g / G);
+        nbm1 |= (m1 < h21 ? 1u : 0u) << (g / G);
       }
     }
     if constexpr (NBL) {
       while (nbm0 | nbm1) {
         const int k = __builtin_ctz(nbm0 | nbm1);
         const unsigned bit = 1u << k;
-        for (int u = 0; u < kGroup; ++u) {
-          const float4 *rec = ftl + (k * kGroup + u) * FREC;
+        for (int u = 0; u < G; ++u) {
+          const float4 *rec = ftl + (k * G + u) * FREC;
           if ((nbm0 & bit) && r2_of<G6MI_PREC_FP32>(f0, rec) < h20) nb_append(nb_count, nb_slot, row0, rec_slot(rec));
           if ((nbm1 & bit) && r2_of<G6MI_PREC_FP32>(f1, rec) < h21) nb_append(nb_count, nb_slot, row1, rec_slot(rec));
         }

@@ -18,6 +18,9 @@ namespace g6mi {
 #ifndef G6MI_GROUP
 #define G6MI_GROUP 16 // j-records per nearest-neighbour group
 #endif
+#ifndef G6MI_SPATIAL_GROUP
+#define G6MI_SPATIAL_GROUP 32 // j-records per group in the spatially ordered kernel
+#endif
 #ifndef G6MI_GROUP_UNROLL
 #define G6MI_GROUP_UNROLL 1 // groups per unrolled loop body
 #endif

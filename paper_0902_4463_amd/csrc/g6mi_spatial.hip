@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kWG, wide_waves<G6MI_PREC_DS>()) void force_spatial
   const int tid = threadIdx.x;
   const int q0 = blockIdx.x * (2 * kWG) + tid, q1 = q0 + kWG;
   const bool v0 = q0 < a.ni, v1 = q1 < a.ni;
-  WideLanes<G6MI_PREC_DS, NBL, true> w;
+  WideLanes<G6MI_PREC_DS, NBL, true, kSpatialGroup> w;
   w.init(a, v0 ? q0 : 0, v1 ? q1 : 0, v0, v1);
   w.row0 = v0 ? sp.iperm[q0] : 0;
   w.row1 = v1 ? sp.iperm[q1] : 0;
