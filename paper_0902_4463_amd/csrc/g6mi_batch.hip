@@ -76,8 +76,9 @@ __device__ __forceinline__ int first_above(const int *inc, int q) {
 // Pass 1 checks the descriptors, picks the block shape of each cluster
 // (kept in its plan entry) and adds up the batch's work; pass 1b cuts the
 // blocks of clusters too small to fill their share of the GPU; pass 2 picks
-// the splits, scans items, i-blocks and partial entries, and fills the
-// item -> cluster and i-block -> cluster tables.
+// the splits, scans i-blocks and partial entries and fills the i-block ->
+// cluster table; pass 3 scans the items class by class (plan_order) and
+// fills the item -> cluster table.
 __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
   const int tid = threadIdx.x;
   if (blockIdx.x > 0) {
@@ -149,15 +150,15 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
   }
   const long long target = plan_target(work, b.grid, b.tune);
 
-  // pass 2: splits, the scans (each thread reads back its own pass-1 entries)
-  // and the item -> cluster and i-block -> cluster tables, filled by all
-  // threads: item (i-block) q of the chunk belongs to the first cluster whose
-  // inclusive item (i-block) count exceeds q
-  int c_items = 0, c_nib = 0;
+  // pass 2: splits, the i-block and partial-entry scans in cluster order
+  // (each thread reads back its own pass-1 entries) and the i-block ->
+  // cluster table, filled by all threads: i-block q of the chunk belongs to
+  // the first cluster whose inclusive i-block count exceeds q
+  int c_nib = 0;
   long long c_pent = 0;
   for (int c0 = 0; c0 < b.ncl; c0 += 256) {
     const int c = c0 + tid;
-    int nsplit = 1, nib = 0, ni = 0;
+    int nib = 0, ni = 0, nsplit = 1;
     BatchPlan pl{};
     if (c < b.ncl) {
       pl = b.plan[c];
@@ -167,26 +168,46 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
       nsplit = pl.nsplit;
     }
     const long long pent = static_cast<long long>(ni) * nsplit;
-    long long items_all, nib_all, pent_all;
-    const int items = static_cast<int>(wg_scan<long long>(static_cast<long long>(nib) * nsplit, s_part, items_all));
+    long long nib_all, pent_all;
     const int nibs = static_cast<int>(wg_scan<long long>(nib, s_part, nib_all));
     const long long pents = wg_scan<long long>(pent, s_part, pent_all);
     if (c < b.ncl) {
       pl.ib0 = c_nib + nibs - nib;
-      pl.item0 = c_items + items - nib * nsplit;
       pl.pbase = c_pent + pents - pent;
       b.plan[c] = pl;
     }
-    s_inc[tid] = items;
     s_inc_ib[tid] = nibs;
     __syncthreads();
-    for (int q = tid; q < items_all; q += 256)
-      if (c_items + q < b.item_cap) b.item_cl[c_items + q] = c0 + first_above(s_inc, q);
     for (int q = tid; q < nib_all; q += 256) b.ib_cl[c_nib + q] = c0 + first_above(s_inc_ib, q);
-    __syncthreads(); // s_inc, s_inc_ib are rewritten by the next chunk
-    c_items += static_cast<int>(items_all);
+    __syncthreads(); // s_inc_ib is rewritten by the next chunk
     c_nib += static_cast<int>(nib_all);
     c_pent += pent_all;
+  }
+  // pass 3: the item scan and the item -> cluster table, one queue class
+  // (plan_order) after the other, in cluster order within a class
+  int c_items = 0;
+  for (int k = 0; k < kItemOrders; ++k) {
+    for (int c0 = 0; c0 < b.ncl; c0 += 256) {
+      const int c = c0 + tid;
+      long long n = 0;
+      BatchPlan pl{};
+      if (c < b.ncl) {
+        pl = b.plan[c];
+        if (plan_order(pl) == k) n = static_cast<long long>(pl.nib) * pl.nsplit;
+      }
+      long long items_all;
+      const int items = static_cast<int>(wg_scan<long long>(n, s_part, items_all));
+      if (n > 0) {
+        pl.item0 = c_items + items - static_cast<int>(n);
+        b.plan[c] = pl;
+      }
+      s_inc[tid] = items;
+      __syncthreads();
+      for (int q = tid; q < items_all; q += 256)
+        if (c_items + q < b.item_cap) b.item_cl[c_items + q] = c0 + first_above(s_inc, q);
+      __syncthreads(); // s_inc is rewritten by the next chunk
+      c_items += static_cast<int>(items_all);
+    }
   }
   if (tid == 0) {
     for (int x = 0; x < kQueues; ++x) b.work->head[x] = 0;

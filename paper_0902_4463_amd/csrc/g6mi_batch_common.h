@@ -78,6 +78,21 @@ __host__ __device__ __forceinline__ void plan_splits(BatchPlan &pl, long long ta
   pl.nsplit = nsplit;
 }
 
+// Queue class of a shaped cluster's items: the item table lists class 0,
+// then 1, then 2, each in cluster order, and the persistent workgroups take
+// items in table order.  Class 0: narrow blocks of fewer than 64
+// i-particles, whose items run several tiles, each a round trip to memory
+// with little arithmetic behind it (long in time, light on the VALU: they
+// run best beside computing items, from the start).  Class 1: wide blocks,
+// the longest computing items.  Class 2: the other narrow blocks, whose
+// items (one or two tiles) are the shortest and fill the end of the launch.
+// Queued in cluster order, the last items were whichever wide blocks came
+// last, and a third of the workgroups idled through the final round.
+constexpr int kItemOrders = 3;
+__host__ __device__ __forceinline__ int plan_order(const BatchPlan &pl) {
+  return pl.ipw == 2 * kWG ? 1 : (pl.ipw < 64 ? 0 : 2);
+}
+
 // Parts per i-block of a batch reduction over nib i-blocks on a grid of
 // `grid` workgroups: the largest power of two up to `cap` (and 64) that
 // still gives every (i-block, part) a workgroup of its own, else 1 (the

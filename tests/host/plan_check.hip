@@ -1,4 +1,4 @@
-// Host check of the batch plan's invariants (plan_shape, plan_share,
+// Host check of the batch plan's invariants (plan_shape, plan_share, plan_order,
 // plan_target, plan_splits, reduce_parts) over seeded random clusters,
 // tunings and grids.  Prints one line per violated invariant and the number
 // of cases; exits 1 on any violation.  Built and run by
@@ -86,6 +86,9 @@ int main() {
     CHECK(static_cast<long long>(pl.per) * pl.nsplit >= ntiles1 &&
               (ntiles1 == 0 || static_cast<long long>(pl.per) * (pl.nsplit - 1) < ntiles1),
           "ntiles=%d per=%d nsplit=%d", ntiles1, pl.per, pl.nsplit);
+    // every shaped cluster has a queue class; wide blocks and only they are class 1
+    const int ord = plan_order(pl);
+    CHECK(ord >= 0 && ord < kItemOrders && ((ord == 1) == (pl.ipw == 2 * kWG)), "ipw=%d order=%d", pl.ipw, ord);
     // the host sizes the item table by (ni / kBatchMinIpw + 1) * max_split per cluster
     CHECK(static_cast<long long>(pl.nib) * pl.nsplit <= (static_cast<long long>(ni) / kBatchMinIpw + 1) * t.max_split,
           "ni=%d nib=%d nsplit=%d", ni, pl.nib, pl.nsplit);
