@@ -97,6 +97,12 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
   if (tid == 0) s_flags = 0;
   __syncthreads();
 
+  // With one chunk (ncl <= 256) each thread keeps its cluster's entry in
+  // registers from pass to pass (pl_last), instead of a round trip through
+  // memory per pass; with more, it reads back its own entry of each chunk.
+  BatchPlan pl_last{};
+  const bool one_chunk = b.ncl <= 256;
+
   // pass 1: validity, block shape, work
   long long c_rows = 0, work = 0;
   for (int c0 = 0; c0 < b.ncl; c0 += 256) {
@@ -123,6 +129,7 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
     if (c < b.ncl && !ok) atomicOr(&s_flags, kFlagBadCluster);
     const BatchPlan pl = plan_shape(ni, nj, b.tune); // splits in pass 2
     if (c < b.ncl) b.plan[c] = pl;
+    pl_last = pl;
     long long work_all;
     wg_scan<long long>(plan_work(pl), s_part, work_all);
     work += work_all;
@@ -137,12 +144,13 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
     const int c = c0 + tid;
     long long w = 0;
     if (c < b.ncl) {
-      BatchPlan pl = b.plan[c];
+      BatchPlan pl = one_chunk ? pl_last : b.plan[c];
       if (pl.nib > 0) {
         const long long share = (static_cast<long long>(b.grid) * plan_work(pl) + work0 - 1) / work0;
         if (plan_share(pl, share, b.tune)) b.plan[c] = pl;
         w = plan_work(pl);
       }
+      pl_last = pl;
     }
     long long work_all;
     wg_scan<long long>(w, s_part, work_all);
@@ -161,7 +169,7 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
     int nib = 0, ni = 0, nsplit = 1;
     BatchPlan pl{};
     if (c < b.ncl) {
-      pl = b.plan[c];
+      pl = one_chunk ? pl_last : b.plan[c];
       plan_splits(pl, target, b.tune);
       nib = pl.nib;
       ni = pl.ni;
@@ -176,6 +184,7 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
       pl.pbase = c_pent + pents - pent;
       b.plan[c] = pl;
     }
+    pl_last = pl;
     s_inc_ib[tid] = nibs;
     __syncthreads();
     for (int q = tid; q < nib_all; q += 256) b.ib_cl[c_nib + q] = c0 + first_above(s_inc_ib, q);
@@ -190,17 +199,13 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs b) {
     for (int c0 = 0; c0 < b.ncl; c0 += 256) {
       const int c = c0 + tid;
       long long n = 0;
-      BatchPlan pl{};
       if (c < b.ncl) {
-        pl = b.plan[c];
+        const BatchPlan pl = one_chunk ? pl_last : b.plan[c];
         if (plan_order(pl) == k) n = static_cast<long long>(pl.nib) * pl.nsplit;
       }
       long long items_all;
       const int items = static_cast<int>(wg_scan<long long>(n, s_part, items_all));
-      if (n > 0) {
-        pl.item0 = c_items + items - static_cast<int>(n);
-        b.plan[c] = pl;
-      }
+      if (n > 0) b.plan[c].item0 = c_items + items - static_cast<int>(n);
       s_inc[tid] = items;
       __syncthreads();
       for (int q = tid; q < items_all; q += 256)
