@@ -266,10 +266,15 @@ __device__ __forceinline__ void pair(const IState<PREC> &st, Sums<real_t<PREC>> 
   }
 }
 
-// The pair terms of Sec. 2.3 added to `acc`; returns r^2 (without
-// softening) for the neighbour search.  No self test: the caller only uses
-// it on tiles that hold no i-particle's own slot.  FIRST: the group's first
-// pair sets the sums instead of adding to them.
+// The pair terms of Sec. 2.3 added to `acc`; returns the softened r^2 + eps2
+// for the neighbour search of the grouped paths: a group's minimum of it
+// picks the group that the exact search re-examines (resolve_group, with
+// r2_of), and is compared with nb_flag_bound(h2, eps2) to flag groups that
+// may hold neighbours.  Forming it with eps2 as the first addend takes one
+// operation fewer per pair than r^2 and then r^2 + eps2; with eps2 = 0 it
+// has the bits of sq3.  No self test: the caller only uses it on tiles that
+// hold no i-particle's own slot.  FIRST: the group's first pair sets the
+// sums instead of adding to them.
 // SELF: the pair is the i-particle with its own record when `self`; its
 // inverse distance is taken as zero (every term then adds an exact zero,
 // also at eps2 = 0) and its r^2 as +inf, so that it is neither a nearest
@@ -281,13 +286,12 @@ __device__ __forceinline__ real_t<PREC> pair_core(const IState<PREC> &st, Sums<r
   using R = real_t<PREC>;
   R d[3], w[3], mj;
   separation<PREC>(st, rec, d, w, mj);
-  R r2u = sq3<PREC>(d);
+  R s = fma(d[2], d[2], fma(d[1], d[1], fma(d[0], d[0], eps2)));
   constexpr bool kInfSelf = SELF && PREC != G6MI_PREC_FP64 && G6MI_SELF_INF;
-  // float32: the self pair's r^2 becomes +inf before the softening, and the
-  // hardware's 1/sqrt(+inf) is +0, so one select serves both uses (float64's
-  // Newton steps would turn +inf * 0 into NaN, so it selects rinv instead)
-  if constexpr (kInfSelf) r2u = self ? R(INFINITY) : r2u;
-  const R s = r2u + eps2;
+  // float32: the self pair's r^2 becomes +inf, and the hardware's
+  // 1/sqrt(+inf) is +0, so one select serves both uses (float64's Newton
+  // steps would turn +inf * 0 into NaN, so it selects rinv instead)
+  if constexpr (kInfSelf) s = self ? R(INFINITY) : s;
   R rinv;
   if constexpr (PREC == G6MI_PREC_FP64) rinv = rsqrt_f64(s);
   else rinv = __builtin_amdgcn_rsqf(s);
@@ -314,8 +318,17 @@ __device__ __forceinline__ real_t<PREC> pair_core(const IState<PREC> &st, Sums<r
       acc.j2[k] += mr3t * d[k];
     }
   }
-  if constexpr (SELF && !kInfSelf) return self ? R(INFINITY) : r2u;
-  else return r2u;
+  if constexpr (SELF && !kInfSelf) return self ? R(INFINITY) : s;
+  else return s;
+}
+
+// Bound for the group neighbour flags, which compare the softened r^2 of
+// pair_core: every pair with r2_of(...) < h2 has a softened r^2 below it,
+// whatever the rounding of the two (each is three rounded operations, some
+// float32 units of the last place; the factor is 16 of them).  A flag only
+// selects a group for the exact test.
+template <class R> __device__ __forceinline__ R nb_flag_bound(R h2, R eps2) {
+  return (h2 + eps2) * R(1.0 + 0x1p-20);
 }
 
 // i-particle `row` of the i-arrays in a's layout.  An invalid row (a padding
@@ -464,9 +477,11 @@ __device__ __forceinline__ void resolve_group(const IState<PREC> &st, int &grp, 
 // min() per pair; once per group the group minimum is compared with the
 // running best and the group's first slot remembered (grp); the exact slot
 // is recovered by re-examining that one group (resolve), where the first
-// minimum wins as in a sequential scan.  Neighbour lists need no per-pair
-// test: a group holds a neighbour of i exactly when its minimum r^2 is below
-// h_i^2, and only such groups are re-examined.  Ragged tiles take the
+// minimum wins as in a sequential scan.  The group minima are of the
+// softened r^2 + eps2 (pair_core), monotone in r^2.  Neighbour lists need no
+// per-pair test: a group may hold a neighbour of i only when its minimum is
+// below nb_flag_bound(h_i^2, eps2), and only such groups are re-examined
+// with the exact test.  Ragged tiles take the
 // per-pair path; tiles that contain an i-particle's own slot take it too, or
 // with SELFG the grouped path with the self pair excluded per pair.
 //
@@ -564,8 +579,9 @@ struct WideLanes {
                                           int *__restrict__ nb_count, int *__restrict__ nb_slot) {
     // own slots relative to the tile (outside 0 .. kTile - 1 when elsewhere)
     const int o0 = slot0 - jbase, o1 = slot1 - jbase;
-    // bit k of nbm0 / nbm1: group k holds a neighbour of i0 / i1
+    // bit k of nbm0 / nbm1: group k may hold a neighbour of i0 / i1
     unsigned nbm0 = 0u, nbm1 = 0u;
+    const R f0 = nb_flag_bound(h20, eps2), f1 = nb_flag_bound(h21, eps2);
 #pragma unroll G6MI_GROUP_UNROLL
     for (int g = 0; g < kTile; g += G) {
       R m0 = R(INFINITY), m1 = R(INFINITY);
@@ -603,9 +619,9 @@ struct WideLanes {
         grp1 = jbase + g;
       }
       if constexpr (NBL) {
-        // the group minimum also tells whether any record is a neighbour
-        nbm0 |= (m0 < h20 ? 1u : 0u) << (g / G);
-        nbm1 |= (m1 < h21 ? 1u : 0u) << (g / G);
+        // the group minimum also tells whether any record may be a neighbour
+        nbm0 |= (m0 < f0 ? 1u : 0u) << (g / G);
+        nbm1 |= (m1 < f1 ? 1u : 0u) << (g / G);
       }
     }
     if constexpr (NBL) {
@@ -644,6 +660,7 @@ struct WideLanes {
     static_assert(PREC == G6MI_PREC_DS, "the far path refines the double-single variant");
     constexpr int FREC = rec4<G6MI_PREC_FP32>();
     unsigned nbm0 = 0u, nbm1 = 0u;
+    const R b0 = nb_flag_bound(h20, eps2), b1 = nb_flag_bound(h21, eps2);
 #pragma unroll G6MI_GROUP_UNROLL
     for (int g = 0; g < kTile; g += G) {
       Sums<R> g0, g1;
@@ -666,8 +683,8 @@ struct WideLanes {
         grp1 = jbase + g;
       }
       if constexpr (NBL) {
-        nbm0 |= (m0 < h20 ? 1u : 0u) << (g / G);
-        nbm1 |= (m1 < h21 ? 1u : 0u) << (g / G);
+        nbm0 |= (m0 < b0 ? 1u : 0u) << (g / G);
+        nbm1 |= (m1 < b1 ? 1u : 0u) << (g / G);
       }
     }
     if constexpr (NBL) {
@@ -750,6 +767,7 @@ struct NarrowLane {
                                           int *__restrict__ nb_count, int *__restrict__ nb_slot) {
     const int o = slot - jbase; // own slot relative to the tile
     unsigned nbm = 0u;
+    const R fb = nb_flag_bound(h2, eps2);
     for (int k0 = 0; k0 < K; k0 += kGroup) {
       R m = R(INFINITY);
       if constexpr (PREC == G6MI_PREC_FP64) {
@@ -773,7 +791,7 @@ struct NarrowLane {
         gbest = m;
         grp = jbase + sub + (k0 << log2L);
       }
-      if constexpr (NBL) nbm |= (m < h2 ? 1u : 0u) << (k0 / kGroup);
+      if constexpr (NBL) nbm |= (m < fb ? 1u : 0u) << (k0 / kGroup);
     }
     if constexpr (NBL) {
       while (nbm) { // rare: append the neighbours of the flagged groups
