@@ -649,11 +649,66 @@ struct WideLanes {
     resolve_group<PREC, SORTED, G>(s1, grp1, 1, src, base, ebest1, eslot1, slot1);
   }
 
+  // Spatially ordered records (src, n of them, in the order of the tiles):
+  // start each particle's running group minimum at a strict upper bound of
+  // its nearest-neighbour search's minimum, the softened r^2 to the record
+  // next to its own (pos + 1, else pos - 1) times 1 + 2^-16, which covers
+  // the few float32 units by which another path (the far separation) may
+  // compute that pair.  A split whose records hold nothing below the bound
+  // then resolves no group and reports no candidate; the split holding the
+  // nearest neighbour resolves it as before, since its group minimum lies
+  // below the bound, so the merged nearest neighbour is unchanged.  Far
+  // tiles farther than the bound need no neighbour work (far_quiet).  A
+  // particle without its own record keeps +inf.
+  __device__ __forceinline__ void seed_nn(const float4 *__restrict__ src, int n, R eps2) {
+    static_assert(SORTED, "the record next to the own one is a near record only in a spatial order");
+    auto bound = [&](const IState<PREC> &st, int pos, bool v) -> R {
+      if (!v || pos < 0 || n < 2) return R(INFINITY);
+      const int k = pos + 1 < n ? pos + 1 : pos - 1;
+      R d[3], w[3], mj;
+      separation<PREC>(st, src + static_cast<size_t>(k) * REC, d, w, mj);
+      const R s = fma(d[2], d[2], fma(d[1], d[1], fma(d[0], d[0], eps2)));
+      return s * R(1.0 + 0x1p-16);
+    };
+    gbest0 = bound(s0, pos0, v0);
+    gbest1 = bound(s1, pos1, v1);
+  }
+
+  // Whether a far tile (every record within rt of the tile's centre, which
+  // rt bounds from above; this lane's i-particles at f0, f1 relative to the
+  // centre) can neither lower this lane's running group minimum of the
+  // softened r^2 nor raise a neighbour flag: the least softened r^2 any of
+  // its records can give, (|x_i - c| - rt)^2 + eps2, exceeds both.  The
+  // factors 1 -+ 2^-18 keep the bound below every computed value: the far
+  // separation and the squares are each within a few float32 units of the
+  // last place (2^-24) of the exact ones.  Then the tile's group minima
+  // would change nothing, and tile_far<false> gives the same results.
+  // Padding lanes take no part.
+  __device__ __forceinline__ bool far_quiet(const IState<G6MI_PREC_FP32> &f0, const IState<G6MI_PREC_FP32> &f1,
+                                            float rt, R eps2) const {
+    static_assert(PREC == G6MI_PREC_DS, "the far path refines the double-single variant");
+    auto least = [&](const IState<G6MI_PREC_FP32> &f) {
+      const float dc = sqrtf(fmaf(f.x[2], f.x[2], fmaf(f.x[1], f.x[1], f.x[0] * f.x[0])));
+      const float gap = fmaxf(dc * (1.0f - 0x1p-18f) - rt * (1.0f + 0x1p-18f), 0.0f);
+      return fmaf(gap, gap, eps2) * (1.0f - 0x1p-18f);
+    };
+    R need0 = gbest0, need1 = gbest1;
+    if constexpr (NBL) {
+      need0 = fmaxf(need0, nb_flag_bound(h20, eps2));
+      need1 = fmaxf(need1, nb_flag_bound(h21, eps2));
+    }
+    return (!v0 || least(f0) > need0) && (!v1 || least(f1) > need1);
+  }
+
   // A full far tile in float32 records relative to the tile's centre
   // (float4{x - c, m}, float4{v, slot}) with the i-particles' positions
   // relative to the same centre in f0, f1 (their velocities as in s0, s1):
   // the grouped path of `tile` with a three-operation separation.  Nearest-
   // neighbour groups are kept by position, as on the DS path.
+  // NN = false: the tile cannot move this lane's nearest-neighbour search or
+  // flag a neighbour (far_quiet), and the pairs add their terms alone; the
+  // sums are those of NN = true.
+  template <bool NN = true>
   __device__ __forceinline__ void tile_far(const float4 *__restrict__ ftl, int jbase, R eps2,
                                            const IState<G6MI_PREC_FP32> &f0, const IState<G6MI_PREC_FP32> &f1,
                                            int *__restrict__ nb_count, int *__restrict__ nb_slot) {
@@ -669,25 +724,31 @@ struct WideLanes {
 #pragma unroll
       for (int u = 1; u < G; ++u) {
         const float4 *rec = ftl + (g + u) * FREC;
-        m0 = fmin(m0, pair_core<G6MI_PREC_FP32>(f0, g0, rec, eps2));
-        m1 = fmin(m1, pair_core<G6MI_PREC_FP32>(f1, g1, rec, eps2));
+        const R q0 = pair_core<G6MI_PREC_FP32>(f0, g0, rec, eps2);
+        const R q1 = pair_core<G6MI_PREC_FP32>(f1, g1, rec, eps2);
+        if constexpr (NN) {
+          m0 = fmin(m0, q0);
+          m1 = fmin(m1, q1);
+        }
       }
       ts0.add(g0);
       ts1.add(g1);
-      if (m0 < gbest0) {
-        gbest0 = m0;
-        grp0 = jbase + g;
-      }
-      if (m1 < gbest1) {
-        gbest1 = m1;
-        grp1 = jbase + g;
-      }
-      if constexpr (NBL) {
-        nbm0 |= (m0 < b0 ? 1u : 0u) << (g / G);
-        nbm1 |= (m1 < b1 ? 1u : 0u) << (g / G);
+      if constexpr (NN) {
+        if (m0 < gbest0) {
+          gbest0 = m0;
+          grp0 = jbase + g;
+        }
+        if (m1 < gbest1) {
+          gbest1 = m1;
+          grp1 = jbase + g;
+        }
+        if constexpr (NBL) {
+          nbm0 |= (m0 < b0 ? 1u : 0u) << (g / G);
+          nbm1 |= (m1 < b1 ? 1u : 0u) << (g / G);
+        }
       }
     }
-    if constexpr (NBL) {
+    if constexpr (NN && NBL) {
       while (nbm0 | nbm1) {
         const int k = __builtin_ctz(nbm0 | nbm1);
         const unsigned bit = 1u << k;

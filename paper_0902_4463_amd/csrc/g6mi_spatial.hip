@@ -280,6 +280,7 @@ __global__ __launch_bounds__(kWG, wide_waves<G6MI_PREC_DS>()) void force_spatial
   w.pos0 = v0 ? sp.spos[q0] : -1;
   w.pos1 = v1 ? sp.spos[q1] : -1;
   const float eps2 = static_cast<float>(a.eps2);
+  w.seed_nn(static_cast<const float4 *>(a.jpred), a.nj, eps2);
 
   // box of this workgroup's i-particles (double-single positions, rounded
   // outwards)
@@ -368,7 +369,11 @@ __global__ __launch_bounds__(kWG, wide_waves<G6MI_PREC_DS>()) void force_spatial
         f1.v[d] = w.s1.v[d];
       }
       __syncthreads();
-      w.tile_far(ftile, jbase, eps2, f0, f1, a.nb_count, a.nb_slot);
+      // a wave whose lanes' neighbour searches the tile cannot touch skips them
+      if (__all(w.far_quiet(f0, f1, c_hi.w, eps2)))
+        w.template tile_far<false>(ftile, jbase, eps2, f0, f1, a.nb_count, a.nb_slot);
+      else
+        w.template tile_far<true>(ftile, jbase, eps2, f0, f1, a.nb_count, a.nb_slot);
     } else {
       w.template tile<true>(tile, jbase, cnt, eps2, a.nb_count, a.nb_slot);
     }
