@@ -308,7 +308,6 @@ __global__ __launch_bounds__(kWG, wide_waves<G6MI_PREC_DS>()) void force_spatial
     if (tid < 6) s_ib[tid] = fkey_value(s_ibk[tid]);
     __syncthreads();
   }
-  const float ib_lo[3] = {s_ib[0], s_ib[1], s_ib[2]}, ib_hi[3] = {s_ib[3], s_ib[4], s_ib[5]};
 
   const int ntiles = (a.nj + kTile - 1) / kTile;
   const int per = (ntiles + gridDim.y - 1) / gridDim.y;
@@ -337,10 +336,12 @@ __global__ __launch_bounds__(kWG, wide_waves<G6MI_PREC_DS>()) void force_spatial
     const int any_self = __syncthreads_or(self_here); // also the barrier after the tile load
     float g2 = 0.0f;
     {
+      // the i-box is read from LDS per tile rather than held in registers
+      // through the tile loop, where registers are scarce
       const float tl[3] = {bmin.x, bmin.y, bmin.z}, th[3] = {bmax.x, bmax.y, bmax.z};
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const float gd = fmaxf(0.0f, fmaxf(tl[d] - ib_hi[d], ib_lo[d] - th[d]));
+        const float gd = fmaxf(0.0f, fmaxf(tl[d] - s_ib[3 + d], s_ib[d] - th[d]));
         g2 += gd * gd;
       }
     }
