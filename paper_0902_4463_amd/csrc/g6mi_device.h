@@ -654,12 +654,14 @@ struct WideLanes {
   // its nearest-neighbour search's minimum, the softened r^2 to the record
   // next to its own (pos + 1, else pos - 1) times 1 + 2^-16, which covers
   // the few float32 units by which another path (the far separation) may
-  // compute that pair.  A split whose records hold nothing below the bound
-  // then resolves no group and reports no candidate; the split holding the
-  // nearest neighbour resolves it as before, since its group minimum lies
-  // below the bound, so the merged nearest neighbour is unchanged.  Far
-  // tiles farther than the bound need no neighbour work (far_quiet).  A
-  // particle without its own record keeps +inf.
+  // compute that pair, plus the least normal float32, which keeps the bound
+  // above a pair at distance zero (eps2 = 0, coincident particles, where
+  // both paths give exactly zero).  A split whose records hold nothing below
+  // the bound then resolves no group and reports no candidate; the split
+  // holding the nearest neighbour resolves it as before, since its group
+  // minimum lies below the bound, so the merged nearest neighbour is
+  // unchanged.  Far tiles farther than the bound need no neighbour work
+  // (far_quiet).  A particle without its own record keeps +inf.
   __device__ __forceinline__ void seed_nn(const float4 *__restrict__ src, int n, R eps2) {
     static_assert(SORTED, "the record next to the own one is a near record only in a spatial order");
     auto bound = [&](const IState<PREC> &st, int pos, bool v) -> R {
@@ -668,7 +670,7 @@ struct WideLanes {
       R d[3], w[3], mj;
       separation<PREC>(st, src + static_cast<size_t>(k) * REC, d, w, mj);
       const R s = fma(d[2], d[2], fma(d[1], d[1], fma(d[0], d[0], eps2)));
-      return s * R(1.0 + 0x1p-16);
+      return fma(s, R(1.0 + 0x1p-16), R(0x1p-126));
     };
     gbest0 = bound(s0, pos0, v0);
     gbest1 = bound(s1, pos1, v1);

@@ -642,6 +642,43 @@ def test_spatial_order_parity(g6, orc, sess, n, ni):
     assert nn["ok"], nn
 
 
+def test_spatial_order_coincident_pairs_at_eps0(g6, orc, sess):
+    """Morton ordering forced on, eps = 0, and 40 pairs of particles with the
+    same predicted position: each member's nearest neighbour is its partner
+    at r^2 = 0.  The kernel starts every particle's nearest-neighbour search
+    below an upper bound taken from the record next to its own, and that
+    bound must stay above a pair at distance zero.  The other particles keep
+    oracle parity of their nearest neighbours (the pairs' forces are not
+    finite and are not compared)."""
+    rng = np.random.default_rng(88)
+    jm = workloads.random_cluster(5000, seed=88)
+    a = rng.permutation(jm.n)[:80]
+    src, dst = a[:40], a[40:]
+    for f in ("x", "v", "a2", "j6", "t"):
+        getattr(jm, f)[dst] = getattr(jm, f)[src]
+    slots = np.arange(jm.n)
+    ref = with_xp(orc, jm, oracle_eval(orc, jm, slots, 0.0, 1e-3))
+    sess.load(jm)
+    try:
+        g6.check(sess.id, g6.g6mi_set_spatial(sess.id, 2))
+        gpu = gpu_eval(sess, g6, jm, slots, ref, 0.0, 1e-3, "ds")
+    finally:
+        g6.g6mi_set_spatial(sess.id, 1)
+    assert gpu["nonfinite"]  # the coincident pairs' forces
+    for u, w in ((src, dst), (dst, src)):
+        assert np.array_equal(gpu["nn_index"][u], jm.index[w])
+        # the i-positions are the oracle's predictions, the records the
+        # library's: the two can differ in the last bits of float64
+        assert np.all(gpu["nn_r2"][a] <= 1e-28)
+    # and many pairs meet at exactly zero, the case the search bound must keep
+    assert np.sum(gpu["nn_r2"][a] == 0.0) >= 20
+    rest = np.setdiff1d(slots, a)
+    xp = ref["_xp"]
+    nn = parity.nn_report(gpu["nn_index"][rest], ref["nn_index"][rest], ref["nn_r2"][rest], xp, jm.index,
+                          ref["xi"][rest])
+    assert nn["ok"], nn
+
+
 def test_spatial_order_neighbour_overflow(g6, orc, sess):
     """Morton ordering forced on with every list overflowing and a shuffled
     index column: partials sit at sorted positions and are mapped back to
