@@ -25,6 +25,14 @@
 // than its own float32 rounding.  Nearer tiles, tiles holding an
 // i-particle's own record and ragged tiles take the double-single path.
 //
+// Far tiles mostly need no neighbour work.  Each particle's nearest-
+// neighbour search starts below a bound taken from the record next to its
+// own in the sorted order (WideLanes::seed_nn), and a wave whose particles
+// all lie farther from a far tile than that bound and the neighbour radius
+// allow walks the tile without the group minima and flags (far_quiet,
+// tile_far<false>): the same sums, about two thirds of an instruction per
+// pair fewer.
+//
 //   sp_init_kernel, sp_bbox_kernel    bounding box of the predicted j (hi parts)
 //   sp_jkeys_kernel, sp_ikeys_kernel  30-bit Morton keys of j and i positions
 //   (rocPRIM radix sort of (key, index) pairs)
