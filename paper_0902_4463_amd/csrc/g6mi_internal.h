@@ -25,7 +25,7 @@ namespace g6mi {
 #define G6MI_GROUP_UNROLL 1 // groups per unrolled loop body
 #endif
 #ifndef G6MI_FAR_K
-#define G6MI_FAR_K 1.0f // far tile: gap to the i-box at least this many tile radii
+#define G6MI_FAR_K 0.75f // far tile: gap to the i-box at least this many tile radii
 #endif
 #ifndef G6MI_FUSED_DEPTH
 #define G6MI_FUSED_DEPTH 3 // records per lane in flight in the one-particle fused kernel

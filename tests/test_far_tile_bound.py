@@ -121,7 +121,7 @@ SCENARIOS = [
 ]
 
 
-@pytest.mark.parametrize("k", [1.0, 2.0])
+@pytest.mark.parametrize("k", [0.75, 1.0, 2.0])
 @pytest.mark.parametrize("name,origin,log_size", SCENARIOS)
 def test_far_separation_within_bound(name, origin, log_size, k):
     rng = np.random.default_rng(zlib.crc32(f"{name} {k}".encode()))
@@ -201,3 +201,22 @@ def test_threshold_tiles_and_float32_centring():
     assert w_kernel <= 4.0 * (1 + 1e-6), w_kernel
     w_f32, _ = worst(f32_centring)
     assert w_f32 > 4.0, w_f32
+
+
+def test_threshold_tiles_at_the_default_criterion():
+    """The library's far criterion, K = 0.75 (G6MI_FAR_K): tiles just past
+    the threshold over several origins stay within 2 (1 + 1/K) = 4.67
+    float32 roundings."""
+    rng = np.random.default_rng(5)
+    k = 0.75
+    worst, n = 0.0, 0
+    for _ in range(400):
+        s = 10.0 ** rng.uniform(-4, -1)
+        xj, xi = threshold_draw(rng, k, rng.choice([0.0, 0.01, 0.3, 1e4]), s)
+        e = far_errors(xj, xi, k)
+        if e is not None:
+            n += 1
+            worst = max(worst, float(e.max()))
+    assert n >= 300, n
+    assert worst <= 2.0 * (1.0 + 1.0 / k) * (1 + 1e-6), worst
+    print(f"K=0.75 threshold tiles: worst |d-D|/(u|D|) = {worst:.3f} over {n} far tiles")

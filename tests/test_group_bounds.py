@@ -92,7 +92,10 @@ def least_softened(b, rt, eps2):
     return (fma32(gap, gap, eps2) * QLO).astype(F32)
 
 
-def far_pairs(xj, xi, k=1.0):
+K_FAR = 0.75  # the library's far criterion (G6MI_FAR_K)
+
+
+def far_pairs(xj, xi, k=K_FAR):
     """For a tile (xj) and an i-block (xi) that the kernel takes as far: the
     far path's softened-r^2 inputs (d per pair), the particles relative to
     the centre and the radius bound; None if the tile is not far."""
@@ -115,7 +118,7 @@ def test_quiet_tile_bound_is_below_every_far_value(eps2):
     slack = []
     for t in range(300):
         s = 10.0 ** rng.uniform(-4, -1)
-        xj, xi = threshold_draw(rng, 1.0, rng.choice([0.0, 0.01, 0.3, 1e4]), s)
+        xj, xi = threshold_draw(rng, K_FAR, rng.choice([0.0, 0.01, 0.3, 1e4]), s)
         if t % 3 == 0:  # i-particles farther out as well
             xi = xi + (xi - xj.mean(axis=0)) * rng.uniform(0, 20)
         got = far_pairs(xj, xi)
@@ -140,7 +143,7 @@ def test_seed_stays_above_the_far_path_value(eps2):
     tiles = 0
     for t in range(200):
         s = 10.0 ** rng.uniform(-4, -1)
-        xj, xi = threshold_draw(rng, 1.0, rng.choice([0.0, 0.01, 0.3, 1e4]), s)
+        xj, xi = threshold_draw(rng, K_FAR, rng.choice([0.0, 0.01, 0.3, 1e4]), s)
         got = far_pairs(xj, xi)
         if got is None:
             continue
