@@ -642,6 +642,30 @@ def test_spatial_order_parity(g6, orc, sess, n, ni):
     assert nn["ok"], nn
 
 
+@pytest.mark.parametrize("eps2", [1e-4, 0.0])
+def test_spatial_order_without_lists(g6, orc, sess, eps2):
+    """The ordered kernel without neighbour lists, where a far tile skips its
+    nearest-neighbour work whenever the searches of a wave's particles cannot
+    move (no neighbour radius holds it back): oracle parity of forces and
+    nearest neighbours, and the same bits as the kernel with lists, whose
+    large neighbour radius here keeps most far tiles on the full path (the
+    skipped work changes no sum and no search)."""
+    jm = workloads.random_cluster(65536, seed=4242)
+    slots = workloads.active_set(jm.n, 20000, seed=7)
+    h2 = 0.05
+    ref = with_xp(orc, jm, oracle_eval(orc, jm, slots, eps2, h2))
+    sess.load(jm)
+    try:
+        g6.check(sess.id, g6.g6mi_set_spatial(sess.id, 2))
+        off = gpu_eval(sess, g6, jm, slots, ref, eps2, h2, "ds", neighbours=False)
+        on = gpu_eval(sess, g6, jm, slots, ref, eps2, h2, "ds")
+    finally:
+        g6.g6mi_set_spatial(sess.id, 1)
+    assert_parity(off, ref, jm, h2, "ds", f"spatial without lists eps2={eps2}")
+    for k in ("acc", "jerk", "pot", "nn_index", "nn_r2"):
+        assert np.array_equal(off[k], on[k]), k
+
+
 def test_spatial_order_coincident_pairs_at_eps0(g6, orc, sess):
     """Morton ordering forced on, eps = 0, and 40 pairs of particles with the
     same predicted position: each member's nearest neighbour is its partner
